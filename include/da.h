@@ -1,0 +1,317 @@
+/*
+ * da.h -- C ABI of dapt, the Digital Annealer's parallel-trial Monte Carlo
+ * step for fully connected QUBO problems on AMD MI355X (gfx950).
+ *
+ * Method: Aramon et al., "Physics-Inspired Optimization for Quadratic
+ * Unconstrained Problems Using a Digital Annealer", arXiv:1806.08815.
+ *   - Algorithm 2 (Sec. II.B): every Monte Carlo step tests a flip of each of
+ *     the N variables in parallel against dE_j - E_offset, applies one of the
+ *     accepted flips chosen uniformly at random, updates all local fields,
+ *     and raises the dynamic offset E_offset when nothing was accepted.
+ *   - Sec. II.D: parallel tempering whose replicas run those steps
+ *     (exchange move of Algorithm 3).
+ *   - Sec. V: the problem is a QUBO, minimise x^T Q x over x in {0,1}^N.
+ *
+ * Conventions shared by every call:
+ *   - E(x) = x^T Q x for any int32 Q (not necessarily symmetric).  Internally
+ *     W_ij = Q_ij + Q_ji (i != j), W_ii = 0, b_i = Q_ii, local field
+ *     h = b + W x, and flipping x_i changes E by (1 - 2 x_i) h_i.
+ *   - Temperatures are in the energy units of Q.  The Metropolis test
+ *     exp(-dE/T) (Sec. III) is decided exactly in integers: a 16-bit draw u
+ *     accepts offset-shifted cost d iff d <= ceil(-T ln((u + 1/2)/65536)) - 1.
+ *   - Random numbers are Philox4x32-10 keyed by the 64-bit seed, with
+ *     counters (variable block, step, replica id, use), so results depend only
+ *     on (instance, schedule, replica id, steps, seed) -- never on batching,
+ *     launch shape or what else runs on the GPU.
+ *   - Energies are int64.  Fields and offsets are int32; da_create rejects
+ *     instances whose fields could leave [-2^30, 2^30].
+ *   - All calls return DA_OK (0) or a negative status; none throws.  A
+ *     da_ctx may be used by one thread at a time; distinct contexts are
+ *     independent.  The last error message of a context is kept for
+ *     da_last_error(ctx); calls without a context keep theirs per thread,
+ *     read with da_last_error(NULL).
+ *   - Host buffers are owned by the caller.  Device buffers passed to the
+ *     *_async calls are owned by the caller and must stay valid until the
+ *     work enqueued on the given stream completes.
+ */
+#ifndef DAPT_DA_H
+#define DAPT_DA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define DA_OK 0
+#define DA_EINVAL (-1)      /* bad argument (null, out of range, inconsistent)  */
+#define DA_ERANGE (-2)      /* coefficients too large for exact int32 fields    */
+#define DA_ENOMEM (-3)      /* device or host allocation failed / over budget   */
+#define DA_EDEVICE (-4)     /* HIP runtime error or no usable gfx950 device     */
+#define DA_ENOTREADY (-5)   /* da_poll: the job has not finished yet            */
+#define DA_ENOTFOUND (-6)   /* da_poll/da_wait: unknown or already-taken ticket */
+
+/* ---- coupling storage types -------------------------------------------- */
+#define DA_DTYPE_AUTO 0     /* smallest exact storage (after a common factor)  */
+#define DA_DTYPE_I8 1
+#define DA_DTYPE_I16 2
+#define DA_DTYPE_I32 4
+
+/* ---- schedules and starts ------------------------------------------------ */
+#define DA_SCHED_GEOMETRIC 0    /* T_l = T_hi (T_lo/T_hi)^(l/(L-1))            */
+#define DA_SCHED_LINEAR_BETA 1  /* 1/T_l linear from 1/T_hi to 1/T_lo (App. A) */
+#define DA_INIT_ZEROS 0         /* common all-zero start (Algorithm 2, App. A) */
+#define DA_INIT_RANDOM 1        /* Philox random start, per replica            */
+
+#define DA_MAX_N 8192           /* next-generation DA size (Sec. II.D)         */
+#define DA_EOFF_MAX (1 << 30)   /* saturation of the dynamic offset            */
+
+typedef struct da_ctx da_ctx;
+
+/* Temperature schedule of an anneal (Algorithm 2: "if due for temperature
+ * update, update the temperature").  An S-step run is cut into n_levels equal
+ * parts; step s uses level floor(s * n_levels / S).  T_hi and T_lo must be
+ * > 0 for DA_SCHED_GEOMETRIC and DA_SCHED_LINEAR_BETA alike, except that
+ * T_hi = T_lo = 0 selects a zero-temperature run (only strictly improving
+ * flips, d < 0).  eoff_inc >= 0 is the offset_increase_rate of Algorithm 2
+ * (0 switches the dynamic offset off, as in the paper's final runs, App. A).
+ * 1 <= n_levels <= 4096. */
+typedef struct da_schedule {
+    double T_hi;
+    double T_lo;
+    int32_t kind;
+    int32_t n_levels;
+    int32_t eoff_inc;
+    int32_t init;
+} da_schedule;
+
+/* Outputs of an anneal for R replicas; every field may be NULL (skipped).
+ * Layouts: best_x/final_x [R][N] uint8 0/1; best_E/final_E/n_accept [R].
+ * best_* is the lowest-energy state seen (initial state included, first one
+ * kept on ties); n_accept counts the steps that applied a flip.
+ * In da_anneal/da_anneal_ex they are host pointers; in the *_async calls
+ * they are device pointers. */
+typedef struct da_result {
+    uint8_t *best_x;
+    int64_t *best_E;
+    uint8_t *final_x;
+    int64_t *final_E;
+    int64_t *n_accept;
+} da_result;
+
+/* Optional per-step trace of an anneal (host pointers, [R][S] each, any may be
+ * NULL): the flipped variable or -1, and E and E_offset after the step.  A
+ * traced run takes a slower kernel variant and exists for verification. */
+typedef struct da_trace {
+    int32_t *k;
+    int64_t *E;
+    int64_t *eoff;
+} da_trace;
+
+/* Launch-shape knobs; zero fields mean "choose automatically" (autotuned
+ * table).  Results never depend on them.
+ *   flips_per_lane      4, 8 or 16 variables per GPU lane
+ *   replicas_per_block  replicas sharing one workgroup (1..16)
+ *   w_in_lds            1: stage W in LDS when it fits; -1: never; 0: auto */
+typedef struct da_launch {
+    int32_t flips_per_lane;
+    int32_t replicas_per_block;
+    int32_t w_in_lds;
+    int32_t reserved;
+} da_launch;
+
+/* What the last kernel launch of a context looked like and how long it took
+ * (HIP events on the launch stream around the main step kernel). */
+typedef struct da_kernel_stats {
+    double kernel_ms;          /* event-timed duration of the step kernel(s) */
+    int64_t launches;          /* step-kernel launches it covers             */
+    int32_t blocks;            /* grid size of the step kernel               */
+    int32_t threads;           /* workgroup size                             */
+    int32_t flips_per_lane;
+    int32_t replicas_per_block;
+    int32_t w_in_lds;
+    int32_t dtype;             /* bytes per stored coupling                  */
+} da_kernel_stats;
+
+/* Static facts about a context. */
+typedef struct da_info {
+    int32_t N;
+    int32_t ld;                /* padded row stride of W on the device       */
+    int32_t dtype;             /* bytes per stored coupling (1, 2, 4)        */
+    int32_t wscale;            /* W = wscale * stored W (common factor)      */
+    int64_t device_bytes;      /* device memory held by the context now     */
+} da_info;
+
+/* Build a context for E(x) = x^T Q x.  Q is N x N int32, row-major, host;
+ * it is copied (the caller keeps its buffer).  Derives W and b (Sec. V),
+ * takes out the greatest common divisor of W as wscale, stores W/wscale in
+ * dtype_hint (or the smallest exact type for DA_DTYPE_AUTO) and uploads W and
+ * b to the current HIP device.  Errors: DA_EINVAL (null, N < 1, N > DA_MAX_N,
+ * bad hint), DA_ERANGE (max_i |b_i| + sum_j |W_ij| > 2^30, or W/wscale does
+ * not fit the forced type), DA_ENOMEM, DA_EDEVICE (no gfx950 device). */
+int da_create(const int32_t *Q, int32_t N, int32_t dtype_hint, da_ctx **out);
+
+/* Frees the context and its device memory; NULL is a no-op. */
+void da_destroy(da_ctx *ctx);
+
+int da_get_info(const da_ctx *ctx, da_info *info);
+
+/* Anneal `replicas` independent runs (Algorithm 2) of `steps` steps each and
+ * copy the outputs to host buffers; synchronous.  Replica ids are
+ * 0..replicas-1.  Same (ctx instance, schedule, replicas, steps, seed) gives
+ * identical outputs.  Errors: DA_EINVAL (null ctx/schedule, replicas < 1,
+ * steps < 0 or >= 2^31, bad schedule), DA_ENOMEM, DA_EDEVICE. */
+int da_anneal(da_ctx *ctx, const da_schedule *schedule, int32_t replicas, int64_t steps,
+              uint64_t seed, da_result *out);
+
+/* As da_anneal, for replica ids replica_base .. replica_base+replicas-1
+ * (replica_base + replicas <= 2^31), with optional launch knobs (NULL = auto)
+ * and an optional per-step trace (NULL = none).  Replica r's outputs are the
+ * same whichever call, batch or launch shape produced them. */
+int da_anneal_ex(da_ctx *ctx, const da_schedule *schedule, int64_t replica_base,
+                 int32_t replicas, int64_t steps, uint64_t seed, const da_launch *launch,
+                 da_result *out, const da_trace *trace);
+
+/* Asynchronous form: enqueue the whole anneal on `stream` (a hipStream_t;
+ * NULL = the null stream) and write outputs to DEVICE buffers in `out_dev`.
+ * Returns once the work is enqueued; the caller synchronises the stream.
+ * Kernel timing for da_last_kernel_stats is recorded with events on the same
+ * stream.  Device scratch (replica state) is owned by the context and reused
+ * by later calls on it, which therefore must be ordered on one stream. */
+int da_anneal_async(da_ctx *ctx, const da_schedule *schedule, int64_t replica_base,
+                    int32_t replicas, int64_t steps, uint64_t seed, const da_launch *launch,
+                    const da_result *out_dev, void *stream);
+
+/* One anneal of a batch (see da_anneal_batch). */
+typedef struct da_batch_item {
+    da_ctx *ctx;
+    da_schedule schedule;
+    int64_t replica_base;
+    int32_t replicas;
+    int32_t reserved;
+    int64_t steps;
+    uint64_t seed;
+    da_result out_dev;         /* device output buffers, as in da_anneal_async */
+} da_batch_item;
+
+/* Run several anneals -- different instances, sizes, coupling types,
+ * schedules and replica counts -- in ONE persistent kernel launch on
+ * `stream`, each with exactly the outputs it would have alone.  Contexts must
+ * be distinct and live on the current device.  Errors as da_anneal_async. */
+int da_anneal_batch(const da_batch_item *items, int32_t count, void *stream);
+
+/* Outputs of parallel tempering, indexed by replica id c*M + m (chain c,
+ * replica m); any field may be NULL.  slot: temperature index of each replica
+ * at the end; n_swaps [chains]: accepted exchanges per chain. */
+typedef struct da_pt_result {
+    uint8_t *best_x;
+    int64_t *best_E;
+    uint8_t *final_x;
+    int64_t *final_E;
+    int64_t *n_accept;
+    int32_t *slot;
+    int64_t *n_swaps;
+} da_pt_result;
+
+/* Parallel tempering with DA steps (Sec. II.D, exchange move of Algorithm 3),
+ * replica exchange on the device.  `chains` independent chains of M replicas
+ * at temperatures temps[0] < ... < temps[M-1] (all > 0); replica m of chain c
+ * has id c*M + m, a random start, and starts at temps[m].  Each of `rounds`
+ * rounds runs steps_per_round DA steps in every replica at its current
+ * temperature (global step t*steps_per_round + q), then for p = 0..M-2 in
+ * order proposes to swap the temperatures of the replicas at temps[p] and
+ * temps[p+1], accepted with probability min(1, exp((1/T_p - 1/T_{p+1})
+ * (E_a - E_b))).  eoff_inc as in da_schedule.  Host outputs; synchronous.
+ * Errors: DA_EINVAL (ladder not strictly increasing or not positive, M < 1,
+ * chains < 1, rounds * steps_per_round >= 2^31), DA_ENOMEM, DA_EDEVICE. */
+int da_pt(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t rounds,
+          int32_t steps_per_round, int32_t eoff_inc, uint64_t seed, da_pt_result *out);
+
+/* Exact E(x) = x^T Q x (int64) of `count` host states x [count][N] (uint8,
+ * nonzero = 1), computed on the device.  Errors: DA_EINVAL, DA_ENOMEM,
+ * DA_EDEVICE. */
+int da_energy(da_ctx *ctx, const uint8_t *x, int32_t count, int64_t *E);
+
+/* Stats of the context's last anneal / PT call (synchronises with its end
+ * event). */
+int da_last_kernel_stats(da_ctx *ctx, da_kernel_stats *stats);
+
+/* Last error message of ctx, or of the calling thread when ctx is NULL. */
+const char *da_last_error(const da_ctx *ctx);
+
+/* Static description of a status code. */
+const char *da_strerror(int status);
+
+/* Host-only: the 65536-entry Metropolis threshold table at temperature T
+ * (thr[u] = ceil(-T ln((u + 1/2)/65536)) - 1 clamped to [-1, 2^30]; all -1
+ * for T <= 0) and the temperature of level l of a schedule.  These are what
+ * the device kernels decide against; exposed for verification. */
+int da_threshold_table(double T, int32_t *thr);
+double da_level_temperature(const da_schedule *schedule, int32_t level);
+
+/* ---- continuous-batching server ----------------------------------------- */
+typedef struct da_server da_server;
+
+/* One solve request.  Q is copied at submit time. */
+typedef struct da_job {
+    const int32_t *Q;
+    int32_t N;
+    int32_t dtype_hint;
+    da_schedule schedule;
+    int32_t replicas;
+    int32_t reserved;
+    int64_t steps;
+    uint64_t seed;
+} da_job;
+
+/* Per-job accounting, seconds on the server's monotonic clock. */
+typedef struct da_job_stats {
+    double t_submit;
+    double t_admit;            /* when its device memory was reserved        */
+    double t_done;             /* when its results were on the host          */
+    int64_t device_bytes;      /* footprint it was admitted with             */
+    int32_t epochs;            /* device epochs it took part in              */
+    int32_t reserved;
+} da_job_stats;
+
+/* Server knobs (zero = default). */
+typedef struct da_server_opts {
+    int64_t epoch_steps;       /* steps each resident job advances per epoch  */
+    int32_t max_resident;      /* cap on concurrently resident jobs           */
+    int32_t reserved;
+} da_server_opts;
+
+/* Start a server that keeps job state resident on the current device and
+ * runs every resident job in shared persistent-kernel epochs.  hbm_budget is
+ * the device memory (bytes) jobs may hold at once.  opts may be NULL. */
+int da_server_create(size_t hbm_budget, const da_server_opts *opts, da_server **out);
+
+/* Queue a job; never blocks on the GPU.  A job that does not fit the free
+ * budget waits and is admitted as memory frees up.  Results equal those of
+ * da_anneal on the same (Q, schedule, replicas, steps, seed), whatever else
+ * is running.  Errors: DA_EINVAL, DA_ERANGE, DA_ENOMEM (the job alone exceeds
+ * the budget). */
+int da_submit(da_server *srv, const da_job *job, uint64_t *ticket);
+
+/* Collect a finished job into host buffers (layouts as da_result, R x N),
+ * releasing its ticket.  DA_ENOTREADY if it is still queued or running.
+ * stats may be NULL. */
+int da_poll(da_server *srv, uint64_t ticket, da_result *out, da_job_stats *stats);
+
+/* As da_poll, but waits for the job. */
+int da_wait(da_server *srv, uint64_t ticket, da_result *out, da_job_stats *stats);
+
+/* Device bytes a job would hold while resident (coupling matrix, fields,
+ * tables, state).  Host-only; the admission policy uses exactly this. */
+int64_t da_job_footprint(int32_t N, int32_t dtype_bytes, int32_t replicas, int32_t n_levels);
+
+/* Drains running jobs, then frees everything; NULL is a no-op. */
+void da_server_destroy(da_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DAPT_DA_H */

@@ -1,0 +1,718 @@
+// da_api.cpp -- the C ABI of include/da.h: contexts, anneals, parallel
+// tempering and energies on one gfx950 device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "da_runtime.h"
+
+using namespace dapt;
+
+namespace dapt {
+
+namespace {
+thread_local std::string t_err;
+}  // namespace
+
+void set_thread_error(const std::string &msg) { t_err = msg; }
+
+int fail(da_ctx *ctx, int code, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    t_err = msg;
+    return code;
+}
+
+int check_hip(da_ctx *ctx, hipError_t e, const char *what) {
+    if (e == hipSuccess) return DA_OK;
+    std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(ctx, e == hipErrorOutOfMemory ? DA_ENOMEM : DA_EDEVICE, msg);
+}
+
+void StateBuf::release() {
+    for (void *p : {(void *)h, (void *)x, (void *)bx, (void *)E, (void *)bE, (void *)eoff,
+                    (void *)nacc})
+        if (p) (void)hipFree(p);
+    h = nullptr; x = bx = nullptr; E = bE = nacc = nullptr; eoff = nullptr;
+    cap = 0;
+}
+
+int64_t StateBuf::bytes_for(int32_t R, int32_t ld) {
+    return (int64_t)R * ld * (4 + 1 + 1) + (int64_t)R * (8 * 3 + 4);
+}
+
+int64_t StateBuf::bytes() const { return bytes_for(cap, ld); }
+
+bool StateBuf::ensure(int32_t R, int32_t ld_, std::string &err) {
+    if (R <= cap && ld_ == ld) return true;
+    release();
+    ld = ld_;
+    const int32_t n = std::max(R, 1);
+    const size_t rows = (size_t)n * ld;
+    if (hipMalloc(&h, rows * 4) != hipSuccess || hipMalloc(&x, rows) != hipSuccess ||
+        hipMalloc(&bx, rows) != hipSuccess || hipMalloc(&E, (size_t)n * 8) != hipSuccess ||
+        hipMalloc(&bE, (size_t)n * 8) != hipSuccess || hipMalloc(&eoff, (size_t)n * 4) != hipSuccess ||
+        hipMalloc(&nacc, (size_t)n * 8) != hipSuccess) {
+        release();
+        err = "out of device memory for replica state";
+        return false;
+    }
+    cap = n;
+    return true;
+}
+
+int validate_schedule(const da_schedule *s, std::string &err) {
+    if (!s) {
+        err = "schedule is null";
+        return DA_EINVAL;
+    }
+    if (s->kind != DA_SCHED_GEOMETRIC && s->kind != DA_SCHED_LINEAR_BETA) {
+        err = "unknown schedule kind";
+        return DA_EINVAL;
+    }
+    if (s->n_levels < 1 || s->n_levels > kMaxLevels) {
+        err = "n_levels must be in [1, 4096]";
+        return DA_EINVAL;
+    }
+    if (s->eoff_inc < 0) {
+        err = "eoff_inc must be >= 0";
+        return DA_EINVAL;
+    }
+    if (s->init != DA_INIT_ZEROS && s->init != DA_INIT_RANDOM) {
+        err = "unknown init";
+        return DA_EINVAL;
+    }
+    const bool zero = (s->T_hi == 0.0 && s->T_lo == 0.0);
+    if (!zero && !(s->T_hi > 0.0 && s->T_lo > 0.0 && std::isfinite(s->T_hi) &&
+                   std::isfinite(s->T_lo))) {
+        err = "temperatures must be finite and > 0 (or both 0)";
+        return DA_EINVAL;
+    }
+    return DA_OK;
+}
+
+// Launch shape: F variables per lane, NW = ceil(N / 64F) waves per replica,
+// RPW replicas per workgroup.  W goes to LDS when small (it then serves every
+// row fetch at LDS latency).
+LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch) {
+    LaunchShape sh;
+    sh.F = (launch && launch->flips_per_lane) ? launch->flips_per_lane : 8;
+    if (sh.F != 4 && sh.F != 8 && sh.F != 16) sh.F = 8;
+    sh.NW = (ctx->N + 64 * sh.F - 1) / (64 * sh.F);
+    while (sh.NW > 16) {  // keep a replica within one workgroup
+        sh.F *= 2;
+        sh.NW = (ctx->N + 64 * sh.F - 1) / (64 * sh.F);
+    }
+    int rpw = (launch && launch->replicas_per_block) ? launch->replicas_per_block : 1;
+    rpw = std::max(1, std::min(rpw, 16 / sh.NW));
+    rpw = std::min(rpw, std::max(R, 1));
+    sh.RPW = rpw;
+    const int64_t w_bytes = (int64_t)ctx->N * ctx->ld * ctx->dtype;
+    const int want = launch ? launch->w_in_lds : 0;
+    sh.w_lds = (want >= 0 && w_bytes <= (want > 0 ? 128 * 1024 : 64 * 1024)) ? 1 : 0;
+    sh.threads = 64 * sh.NW * sh.RPW;
+    sh.blocks = (R + sh.RPW - 1) / sh.RPW;
+    sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, sh.w_lds ? (int)w_bytes : 0);
+    if (sh.lds > 160 * 1024 && sh.w_lds) {
+        sh.w_lds = 0;
+        sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0);
+    }
+    return sh;
+}
+
+JobDesc make_job(const da_ctx *ctx, const LevelTables &lt, int32_t R, uint32_t rid_base,
+                 uint64_t seed, int64_t steps, const da_schedule &s, const LaunchShape &sh) {
+    JobDesc J{};
+    J.W = ctx->d_W;
+    J.b = ctx->d_b;
+    J.N = ctx->N;
+    J.ld = ctx->ld;
+    J.dtype = ctx->dtype;
+    J.wscale = ctx->wscale;
+    J.h = ctx->st.h;
+    J.x = ctx->st.x;
+    J.bx = ctx->st.bx;
+    J.E = ctx->st.E;
+    J.bE = ctx->st.bE;
+    J.eoff = ctx->st.eoff;
+    J.nacc = ctx->st.nacc;
+    J.R = R;
+    J.rid_base = rid_base;
+    J.seed = seed;
+    J.s0 = 0;
+    J.s1 = steps;
+    J.S = steps;
+    J.L = lt.L;
+    J.eoff_inc = s.eoff_inc;
+    J.lvl_of_rep = nullptr;
+    J.round_ptr = nullptr;
+    J.K = 0;
+    J.NW = sh.NW;
+    J.RPW = sh.RPW;
+    J.w_lds = sh.w_lds;
+    J.hdr = lt.d_hdr;
+    J.brk = lt.d_brk;
+    J.thr = lt.d_thr;
+    return J;
+}
+
+int init_state(da_ctx *ctx, const JobDesc &J, int init, hipStream_t stream) {
+    int e;
+    if (init == DA_INIT_ZEROS) {
+        e = launch_state_zero(J, stream);
+    } else {
+        e = launch_rand_bits(J.x, J.R, J.N, J.ld, J.rid_base, J.seed, stream);
+        if (!e) e = launch_fields(J, J.x, J.R, J.h, stream);
+        if (!e) e = launch_energy_from_fields(J, J.x, J.h, J.R, J.E, true, stream);
+    }
+    return check_hip(ctx, (hipError_t)e, "state initialisation launch");
+}
+
+}  // namespace dapt
+
+namespace {
+
+constexpr int64_t kMaxSteps = (int64_t(1) << 31) - 1;
+
+bool device_is_gfx950(std::string &err) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        err = std::string("no HIP device: ") + hipGetErrorString(e);
+        return false;
+    }
+    hipDeviceProp_t p;
+    e = hipGetDeviceProperties(&p, dev);
+    if (e != hipSuccess) {
+        err = std::string("hipGetDeviceProperties failed: ") + hipGetErrorString(e);
+        return false;
+    }
+    if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0) {
+        err = std::string("device is ") + p.gcnArchName + ", this library is built for gfx950";
+        return false;
+    }
+    return true;
+}
+
+int64_t gcd64(int64_t a, int64_t b) {
+    a = a < 0 ? -a : a;
+    b = b < 0 ? -b : b;
+    while (b) {
+        const int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+hipStream_t ctx_stream(da_ctx *ctx, void *stream) {
+    return stream ? reinterpret_cast<hipStream_t>(stream) : ctx->own_stream;
+}
+
+// Copy-out of one anneal's outputs from the context state into device buffers.
+int extract_outputs(da_ctx *ctx, const JobDesc &J, int32_t R, const da_result *o, hipStream_t s) {
+    int e = 0;
+    if (o->best_x && !e) e = launch_extract(J, J.bx, o->best_x, R, s);
+    if (o->final_x && !e) e = launch_extract(J, J.x, o->final_x, R, s);
+    if (o->best_E && !e) e = launch_copy_i64(J.bE, o->best_E, R, s);
+    if (o->final_E && !e) e = launch_copy_i64(J.E, o->final_E, R, s);
+    if (o->n_accept && !e) e = launch_copy_i64(J.nacc, o->n_accept, R, s);
+    return check_hip(ctx, (hipError_t)e, "output extraction launch");
+}
+
+int copy_outputs_to_host(da_ctx *ctx, const JobDesc &J, int32_t R, const da_result *o,
+                         hipStream_t s) {
+    hipError_t e = hipSuccess;
+    const size_t N = (size_t)J.N, ld = (size_t)J.ld;
+    if (o->best_x && e == hipSuccess)
+        e = hipMemcpy2DAsync(o->best_x, N, J.bx, ld, N, (size_t)R, hipMemcpyDeviceToHost, s);
+    if (o->final_x && e == hipSuccess)
+        e = hipMemcpy2DAsync(o->final_x, N, J.x, ld, N, (size_t)R, hipMemcpyDeviceToHost, s);
+    if (o->best_E && e == hipSuccess)
+        e = hipMemcpyAsync(o->best_E, J.bE, (size_t)R * 8, hipMemcpyDeviceToHost, s);
+    if (o->final_E && e == hipSuccess)
+        e = hipMemcpyAsync(o->final_E, J.E, (size_t)R * 8, hipMemcpyDeviceToHost, s);
+    if (o->n_accept && e == hipSuccess)
+        e = hipMemcpyAsync(o->n_accept, J.nacc, (size_t)R * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return check_hip(ctx, e, "copy of outputs to host");
+}
+
+void record_stats(da_ctx *ctx, const LaunchShape &sh, int64_t launches) {
+    ctx->last = da_kernel_stats{};
+    ctx->last.launches = launches;
+    ctx->last.blocks = sh.blocks;
+    ctx->last.threads = sh.threads;
+    ctx->last.flips_per_lane = sh.F;
+    ctx->last.replicas_per_block = sh.RPW;
+    ctx->last.w_in_lds = sh.w_lds;
+    ctx->last.dtype = ctx->dtype;
+    ctx->have_stats = true;
+}
+
+// Enqueue a full anneal: state init, step kernel between timing events.
+int enqueue_anneal(da_ctx *ctx, const da_schedule *schedule, int64_t replica_base,
+                   int32_t replicas, int64_t steps, uint64_t seed, const da_launch *launch,
+                   const da_trace *trace_dev, hipStream_t s, JobDesc &J) {
+    std::string err;
+    if (!ctx) return fail(nullptr, DA_EINVAL, "ctx is null");
+    int rc = validate_schedule(schedule, err);
+    if (rc) return fail(ctx, rc, err);
+    if (replicas < 1) return fail(ctx, DA_EINVAL, "replicas must be >= 1");
+    if (steps < 0 || steps > kMaxSteps) return fail(ctx, DA_EINVAL, "steps must be in [0, 2^31)");
+    if (replica_base < 0 || replica_base + replicas > (int64_t(1) << 31))
+        return fail(ctx, DA_EINVAL, "replica ids must lie in [0, 2^31)");
+    auto lt = get_level_tables(schedule_temps(*schedule), err);
+    if (!lt) return fail(ctx, DA_ENOMEM, err);
+    ctx->keep_tables = lt;
+    if (!ctx->st.ensure(replicas, ctx->ld, err)) return fail(ctx, DA_ENOMEM, err);
+    const LaunchShape sh = choose_shape(ctx, replicas, launch);
+    J = make_job(ctx, *lt, replicas, (uint32_t)replica_base, seed, steps, *schedule, sh);
+    rc = init_state(ctx, J, schedule->init, s);
+    if (rc) return rc;
+    rc = check_hip(ctx, hipEventRecord(ctx->ev0, s), "event record");
+    if (rc) return rc;
+    if (steps > 0) {
+        TraceDesc T{nullptr, nullptr, nullptr, steps};
+        if (trace_dev) {
+            T.k = trace_dev->k;
+            T.E = trace_dev->E;
+            T.eoff = trace_dev->eoff;
+        }
+        const int e = launch_run(J, sh.F, trace_dev ? &T : nullptr, sh.blocks, sh.threads, sh.lds, s);
+        rc = check_hip(ctx, (hipError_t)e, "step kernel launch");
+        if (rc) return rc;
+    }
+    rc = check_hip(ctx, hipEventRecord(ctx->ev1, s), "event record");
+    if (rc) return rc;
+    record_stats(ctx, sh, steps > 0 ? 1 : 0);
+    return DA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int da_create(const int32_t *Q, int32_t N, int32_t dtype_hint, da_ctx **out) {
+    if (!out) return fail(nullptr, DA_EINVAL, "out is null");
+    *out = nullptr;
+    if (!Q) return fail(nullptr, DA_EINVAL, "Q is null");
+    if (N < 1 || N > DA_MAX_N) return fail(nullptr, DA_EINVAL, "N must be in [1, 8192]");
+    if (dtype_hint != DA_DTYPE_AUTO && dtype_hint != DA_DTYPE_I8 && dtype_hint != DA_DTYPE_I16 &&
+        dtype_hint != DA_DTYPE_I32)
+        return fail(nullptr, DA_EINVAL, "unknown dtype hint");
+    std::string err;
+    if (!device_is_gfx950(err)) return fail(nullptr, DA_EDEVICE, err);
+
+    // W_ij = Q_ij + Q_ji off the diagonal, b_i = Q_ii (E = x^T Q x).
+    const size_t n = (size_t)N;
+    std::vector<int64_t> W(n * n);
+    std::vector<int64_t> b(n);
+    int64_t g = 0, maxrow = 0;
+    for (size_t i = 0; i < n; ++i) {
+        b[i] = Q[i * n + i];
+        int64_t row = b[i] < 0 ? -b[i] : b[i];
+        for (size_t j = 0; j < n; ++j) {
+            const int64_t w = (i == j) ? 0 : (int64_t)Q[i * n + j] + (int64_t)Q[j * n + i];
+            W[i * n + j] = w;
+            row += w < 0 ? -w : w;
+            if (w) g = gcd64(g, w);
+        }
+        maxrow = std::max(maxrow, row);
+    }
+    if (maxrow > (int64_t(1) << 30))
+        return fail(nullptr, DA_ERANGE,
+                    "max_i |b_i| + sum_j |W_ij| exceeds 2^30: fields would not fit int32");
+    if (g == 0) g = 1;
+    int64_t maxw = 0;
+    for (auto w : W) maxw = std::max(maxw, (w < 0 ? -w : w) / g);
+    int dtype = dtype_hint;
+    if (dtype == DA_DTYPE_AUTO) dtype = maxw <= 127 ? 1 : (maxw <= 32767 ? 2 : 4);
+    const int64_t lim = dtype == 1 ? 127 : (dtype == 2 ? 32767 : 2147483647);
+    if (maxw > lim) return fail(nullptr, DA_ERANGE, "couplings do not fit the requested type");
+
+    da_ctx *ctx = new (std::nothrow) da_ctx();
+    if (!ctx) return fail(nullptr, DA_ENOMEM, "host allocation failed");
+    ctx->N = N;
+    ctx->ld = (N + 63) / 64 * 64;
+    ctx->dtype = dtype;
+    ctx->wscale = (int32_t)g;
+    (void)hipGetDevice(&ctx->device);
+    const size_t ld = (size_t)ctx->ld;
+    std::vector<uint8_t> Wd(ld * ld * (size_t)dtype, 0);
+    for (size_t i = 0; i < n; ++i)
+        for (size_t j = 0; j < n; ++j) {
+            const int64_t v = W[i * n + j] / g;
+            void *dst = Wd.data() + (i * ld + j) * (size_t)dtype;
+            if (dtype == 1) { int8_t t = (int8_t)v; std::memcpy(dst, &t, 1); }
+            else if (dtype == 2) { int16_t t = (int16_t)v; std::memcpy(dst, &t, 2); }
+            else { int32_t t = (int32_t)v; std::memcpy(dst, &t, 4); }
+        }
+    std::vector<int32_t> bd(ld, 0);
+    for (size_t i = 0; i < n; ++i) bd[i] = (int32_t)b[i];
+    int rc = check_hip(nullptr, hipMalloc(&ctx->d_W, Wd.size()), "W allocation");
+    if (!rc) rc = check_hip(nullptr, hipMalloc(&ctx->d_b, ld * 4), "b allocation");
+    if (!rc) rc = check_hip(nullptr, hipMemcpy(ctx->d_W, Wd.data(), Wd.size(), hipMemcpyHostToDevice), "W upload");
+    if (!rc) rc = check_hip(nullptr, hipMemcpy(ctx->d_b, bd.data(), ld * 4, hipMemcpyHostToDevice), "b upload");
+    if (!rc) rc = check_hip(nullptr, hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking), "stream");
+    if (!rc) rc = check_hip(nullptr, hipEventCreate(&ctx->ev0), "event");
+    if (!rc) rc = check_hip(nullptr, hipEventCreate(&ctx->ev1), "event");
+    if (rc) {
+        da_destroy(ctx);
+        return rc;
+    }
+    *out = ctx;
+    return DA_OK;
+}
+
+void da_destroy(da_ctx *ctx) {
+    if (!ctx) return;
+    if (ctx->own_stream) (void)hipStreamSynchronize(ctx->own_stream);
+    (void)hipDeviceSynchronize();
+    ctx->st.release();
+    if (ctx->d_W) (void)hipFree(ctx->d_W);
+    if (ctx->d_b) (void)hipFree(ctx->d_b);
+    for (void *p : {(void *)ctx->pt_slot2rep, (void *)ctx->pt_lvl, (void *)ctx->pt_swaps,
+                    (void *)ctx->pt_round, (void *)ctx->pt_dbeta, (void *)ctx->pt_lnU})
+        if (p) (void)hipFree(p);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
+    delete ctx;
+}
+
+int da_get_info(const da_ctx *ctx, da_info *info) {
+    if (!ctx || !info) return fail(nullptr, DA_EINVAL, "null argument");
+    info->N = ctx->N;
+    info->ld = ctx->ld;
+    info->dtype = ctx->dtype;
+    info->wscale = ctx->wscale;
+    info->device_bytes = (int64_t)ctx->ld * ctx->ld * ctx->dtype + (int64_t)ctx->ld * 4 +
+                         ctx->st.bytes();
+    return DA_OK;
+}
+
+int da_anneal_async(da_ctx *ctx, const da_schedule *schedule, int64_t replica_base,
+                    int32_t replicas, int64_t steps, uint64_t seed, const da_launch *launch,
+                    const da_result *out_dev, void *stream) {
+    if (!ctx) return fail(nullptr, DA_EINVAL, "ctx is null");
+    hipStream_t s = ctx_stream(ctx, stream);
+    JobDesc J;
+    int rc = enqueue_anneal(ctx, schedule, replica_base, replicas, steps, seed, launch, nullptr, s, J);
+    if (rc) return rc;
+    if (out_dev) rc = extract_outputs(ctx, J, replicas, out_dev, s);
+    return rc;
+}
+
+int da_anneal_ex(da_ctx *ctx, const da_schedule *schedule, int64_t replica_base,
+                 int32_t replicas, int64_t steps, uint64_t seed, const da_launch *launch,
+                 da_result *out, const da_trace *trace) {
+    if (!ctx) return fail(nullptr, DA_EINVAL, "ctx is null");
+    hipStream_t s = ctx->own_stream;
+    da_trace dev_trace{nullptr, nullptr, nullptr};
+    const size_t cells = (size_t)std::max<int64_t>(replicas, 0) * (size_t)std::max<int64_t>(steps, 0);
+    int rc = DA_OK;
+    if (trace && cells) {
+        if (trace->k) rc = check_hip(ctx, hipMalloc(&dev_trace.k, cells * 4), "trace allocation");
+        if (!rc && trace->E) rc = check_hip(ctx, hipMalloc(&dev_trace.E, cells * 8), "trace allocation");
+        if (!rc && trace->eoff) rc = check_hip(ctx, hipMalloc(&dev_trace.eoff, cells * 8), "trace allocation");
+        // the traced kernel writes every column it is given; give it all three
+        if (!rc && !dev_trace.k) rc = check_hip(ctx, hipMalloc(&dev_trace.k, cells * 4), "trace allocation");
+        if (!rc && !dev_trace.E) rc = check_hip(ctx, hipMalloc(&dev_trace.E, cells * 8), "trace allocation");
+        if (!rc && !dev_trace.eoff) rc = check_hip(ctx, hipMalloc(&dev_trace.eoff, cells * 8), "trace allocation");
+    }
+    JobDesc J;
+    if (!rc)
+        rc = enqueue_anneal(ctx, schedule, replica_base, replicas, steps, seed, launch,
+                            (trace && cells) ? &dev_trace : nullptr, s, J);
+    if (!rc && out) rc = copy_outputs_to_host(ctx, J, replicas, out, s);
+    if (!rc && trace && cells) {
+        hipError_t e = hipSuccess;
+        if (trace->k) e = hipMemcpy(trace->k, dev_trace.k, cells * 4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && trace->E) e = hipMemcpy(trace->E, dev_trace.E, cells * 8, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && trace->eoff) e = hipMemcpy(trace->eoff, dev_trace.eoff, cells * 8, hipMemcpyDeviceToHost);
+        rc = check_hip(ctx, e, "trace copy");
+    }
+    if (!rc && !out) rc = check_hip(ctx, hipStreamSynchronize(s), "stream synchronise");
+    if (dev_trace.k) (void)hipFree(dev_trace.k);
+    if (dev_trace.E) (void)hipFree(dev_trace.E);
+    if (dev_trace.eoff) (void)hipFree(dev_trace.eoff);
+    return rc;
+}
+
+int da_anneal(da_ctx *ctx, const da_schedule *schedule, int32_t replicas, int64_t steps,
+              uint64_t seed, da_result *out) {
+    return da_anneal_ex(ctx, schedule, 0, replicas, steps, seed, nullptr, out, nullptr);
+}
+
+int da_anneal_batch(const da_batch_item *items, int32_t count, void *stream) {
+    if (!items || count < 1) return fail(nullptr, DA_EINVAL, "empty batch");
+    hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : nullptr;
+    for (int32_t a = 0; a < count; ++a)
+        for (int32_t c = a + 1; c < count; ++c)
+            if (items[a].ctx == items[c].ctx)
+                return fail(nullptr, DA_EINVAL, "batch items must use distinct contexts");
+    std::vector<JobDesc> jobs((size_t)count);
+    std::vector<BatchItem> work;
+    size_t lds = 0;
+    std::vector<std::shared_ptr<LevelTables>> keep;
+    for (int32_t a = 0; a < count; ++a) {
+        const da_batch_item &it = items[a];
+        da_ctx *ctx = it.ctx;
+        if (!ctx) return fail(nullptr, DA_EINVAL, "batch item without context");
+        if (!s) s = ctx->own_stream;
+        std::string err;
+        int rc = validate_schedule(&it.schedule, err);
+        if (rc) return fail(ctx, rc, err);
+        if (it.replicas < 1 || it.steps < 0 || it.steps > kMaxSteps || it.replica_base < 0 ||
+            it.replica_base + it.replicas > (int64_t(1) << 31))
+            return fail(ctx, DA_EINVAL, "bad replicas / steps / replica_base in batch item");
+        auto lt = get_level_tables(schedule_temps(it.schedule), err);
+        if (!lt) return fail(ctx, DA_ENOMEM, err);
+        keep.push_back(lt);
+        ctx->keep_tables = lt;
+        if (!ctx->st.ensure(it.replicas, ctx->ld, err)) return fail(ctx, DA_ENOMEM, err);
+        // every workgroup of the persistent launch has 16 waves
+        da_launch shape_req{8, 16, -1, 0};
+        LaunchShape sh = choose_shape(ctx, it.replicas, &shape_req);
+        sh.RPW = 16 / sh.NW;
+        sh.w_lds = 0;
+        sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0);
+        if (sh.F != 8) return fail(ctx, DA_EINVAL, "batched launch needs N <= 8192");
+        lds = std::max(lds, sh.lds);
+        jobs[(size_t)a] = make_job(ctx, *lt, it.replicas, (uint32_t)it.replica_base, it.seed,
+                                   it.steps, it.schedule, sh);
+        rc = init_state(ctx, jobs[(size_t)a], it.schedule.init, s);
+        if (rc) return rc;
+        if (it.steps > 0)
+            for (int32_t r0 = 0; r0 < it.replicas; r0 += sh.RPW) work.push_back(BatchItem{a, r0});
+        record_stats(ctx, sh, 1);
+    }
+    // longest jobs first so the tail of the persistent launch is short
+    std::stable_sort(work.begin(), work.end(), [&](const BatchItem &p, const BatchItem &q) {
+        const int64_t cp = jobs[(size_t)p.job].S * jobs[(size_t)p.job].NW;
+        const int64_t cq = jobs[(size_t)q.job].S * jobs[(size_t)q.job].NW;
+        return cp > cq;
+    });
+    da_ctx *c0 = items[0].ctx;
+    JobDesc *d_jobs = nullptr;
+    BatchItem *d_items = nullptr;
+    int32_t *d_counter = nullptr;
+    int rc = check_hip(c0, hipMalloc(&d_jobs, jobs.size() * sizeof(JobDesc)), "batch allocation");
+    if (!rc) rc = check_hip(c0, hipMalloc(&d_items, std::max<size_t>(work.size(), 1) * sizeof(BatchItem)), "batch allocation");
+    if (!rc) rc = check_hip(c0, hipMalloc(&d_counter, 4), "batch allocation");
+    if (!rc) rc = check_hip(c0, hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * sizeof(JobDesc), hipMemcpyHostToDevice, s), "batch upload");
+    if (!rc && !work.empty()) rc = check_hip(c0, hipMemcpyAsync(d_items, work.data(), work.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s), "batch upload");
+    if (!rc) rc = check_hip(c0, (hipError_t)launch_fill_i32(d_counter, 0, 1, s), "counter reset");
+    if (!rc) rc = check_hip(c0, hipEventRecord(c0->ev0, s), "event record");
+    if (!rc && !work.empty()) {
+        int dev = 0, cus = 256;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        const int per_cu = lds > 80 * 1024 ? 1 : 2;
+        const int blocks = (int)std::min<size_t>(work.size(), (size_t)cus * per_cu);
+        rc = check_hip(c0, (hipError_t)launch_batch(d_jobs, d_items, (int)work.size(), d_counter,
+                                                      blocks, 1024, lds, s),
+                       "batch kernel launch");
+        c0->last.blocks = blocks;
+        c0->last.threads = 1024;
+    }
+    if (!rc) rc = check_hip(c0, hipEventRecord(c0->ev1, s), "event record");
+    for (int32_t a = 0; a < count && !rc; ++a)
+        rc = extract_outputs(items[a].ctx, jobs[(size_t)a], items[a].replicas, &items[a].out_dev, s);
+    // the device tables of the batch must outlive the kernel
+    (void)hipStreamSynchronize(s);
+    if (d_jobs) (void)hipFree(d_jobs);
+    if (d_items) (void)hipFree(d_items);
+    if (d_counter) (void)hipFree(d_counter);
+    return rc;
+}
+
+int da_pt(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t rounds,
+          int32_t steps_per_round, int32_t eoff_inc, uint64_t seed, da_pt_result *out) {
+    if (!ctx) return fail(nullptr, DA_EINVAL, "ctx is null");
+    if (!temps || M < 1 || M > kMaxLevels || chains < 1 || rounds < 0 || steps_per_round < 0 ||
+        eoff_inc < 0)
+        return fail(ctx, DA_EINVAL, "bad PT arguments");
+    if ((int64_t)M * chains > (int64_t(1) << 30)) return fail(ctx, DA_EINVAL, "too many replicas");
+    if (rounds * (int64_t)steps_per_round > kMaxSteps || rounds > kMaxSteps)
+        return fail(ctx, DA_EINVAL, "rounds * steps_per_round must be < 2^31");
+    for (int p = 0; p < M; ++p) {
+        if (!(temps[p] > 0.0) || !std::isfinite(temps[p]))
+            return fail(ctx, DA_EINVAL, "temperatures must be finite and > 0");
+        if (p + 1 < M && !(temps[p] < temps[p + 1]))
+            return fail(ctx, DA_EINVAL, "temperatures must be strictly increasing");
+    }
+    const int32_t R = M * chains;
+    std::string err;
+    std::vector<double> tv(temps, temps + M);
+    auto lt = get_level_tables(tv, err);
+    if (!lt) return fail(ctx, DA_ENOMEM, err);
+    ctx->keep_tables = lt;
+    if (!ctx->st.ensure(R, ctx->ld, err)) return fail(ctx, DA_ENOMEM, err);
+    hipStream_t s = ctx->own_stream;
+    int rc = DA_OK;
+    if (R > ctx->pt_cap_R || M > ctx->pt_cap_M || chains > ctx->pt_cap_chains) {
+        for (void *p : {(void *)ctx->pt_slot2rep, (void *)ctx->pt_lvl, (void *)ctx->pt_swaps,
+                        (void *)ctx->pt_round, (void *)ctx->pt_dbeta, (void *)ctx->pt_lnU})
+            if (p) (void)hipFree(p);
+        ctx->pt_slot2rep = ctx->pt_lvl = nullptr;
+        ctx->pt_swaps = nullptr;
+        ctx->pt_round = nullptr;
+        ctx->pt_dbeta = ctx->pt_lnU = nullptr;
+        ctx->pt_cap_R = ctx->pt_cap_M = ctx->pt_cap_chains = 0;
+        rc = check_hip(ctx, hipMalloc(&ctx->pt_slot2rep, (size_t)R * 4), "PT allocation");
+        if (!rc) rc = check_hip(ctx, hipMalloc(&ctx->pt_lvl, (size_t)R * 4), "PT allocation");
+        if (!rc) rc = check_hip(ctx, hipMalloc(&ctx->pt_swaps, (size_t)chains * 8), "PT allocation");
+        if (!rc) rc = check_hip(ctx, hipMalloc(&ctx->pt_round, 4), "PT allocation");
+        if (!rc) rc = check_hip(ctx, hipMalloc(&ctx->pt_dbeta, (size_t)M * 8), "PT allocation");
+        if (!rc) rc = check_hip(ctx, hipMalloc(&ctx->pt_lnU, 65536 * 8), "PT allocation");
+        if (rc) return rc;
+        ctx->pt_cap_R = R;
+        ctx->pt_cap_M = M;
+        ctx->pt_cap_chains = chains;
+    }
+    // exchange tables: 1/T_p - 1/T_{p+1} and ln U_u, U_u = (u + 1/2)/65536
+    std::vector<double> dbeta((size_t)M, 0.0), lnU(65536);
+    for (int p = 0; p + 1 < M; ++p) dbeta[(size_t)p] = 1.0 / temps[p] - 1.0 / temps[p + 1];
+    for (int u = 0; u < 65536; ++u) lnU[(size_t)u] = std::log(((double)u + 0.5) / 65536.0);
+    rc = check_hip(ctx, hipMemcpyAsync(ctx->pt_dbeta, dbeta.data(), (size_t)M * 8, hipMemcpyHostToDevice, s), "PT upload");
+    if (!rc) rc = check_hip(ctx, hipMemcpyAsync(ctx->pt_lnU, lnU.data(), 65536 * 8, hipMemcpyHostToDevice, s), "PT upload");
+    if (rc) return rc;
+
+    da_schedule sched{temps[0], temps[0], DA_SCHED_GEOMETRIC, 1, eoff_inc, DA_INIT_RANDOM};
+    const LaunchShape sh = choose_shape(ctx, R, nullptr);
+    JobDesc J = make_job(ctx, *lt, R, 0u, seed, 0, sched, sh);
+    J.L = M;
+    J.lvl_of_rep = ctx->pt_lvl;
+    J.round_ptr = ctx->pt_round;
+    J.K = steps_per_round;
+    rc = init_state(ctx, J, DA_INIT_RANDOM, s);
+    if (!rc) rc = check_hip(ctx, (hipError_t)launch_pt_setup(ctx->pt_slot2rep, ctx->pt_lvl, ctx->pt_swaps, ctx->pt_round, M, chains, s), "PT setup");
+    if (!rc) rc = check_hip(ctx, hipEventRecord(ctx->ev0, s), "event record");
+    if (rc) return rc;
+
+    auto one_round = [&]() -> int {
+        int e = 0;
+        if (steps_per_round > 0) e = launch_run(J, sh.F, nullptr, sh.blocks, sh.threads, sh.lds, s);
+        if (!e)
+            e = launch_pt_exchange(J.E, ctx->pt_slot2rep, ctx->pt_lvl, ctx->pt_dbeta, ctx->pt_lnU, M,
+                                   chains, seed, ctx->pt_round, ctx->pt_swaps, s);
+        return e;
+    };
+    // Rounds are captured into a hipGraph (kernels only, no memsets) and
+    // replayed; each kernel reads the round index from the device counter.
+    const int64_t G = std::min<int64_t>(rounds, 32);
+    int64_t done = 0;
+    if (G >= 2 && rounds >= 2 * G) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        rc = check_hip(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "graph capture");
+        for (int64_t q = 0; q < G && !rc; ++q) rc = check_hip(ctx, (hipError_t)one_round(), "PT round launch");
+        hipError_t ee = hipStreamEndCapture(s, &graph);
+        if (!rc) rc = check_hip(ctx, ee, "graph capture end");
+        if (!rc) rc = check_hip(ctx, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate");
+        for (; !rc && done + G <= rounds; done += G)
+            rc = check_hip(ctx, hipGraphLaunch(exec, s), "graph launch");
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (rc) return rc;
+    }
+    for (; done < rounds && !rc; ++done) rc = check_hip(ctx, (hipError_t)one_round(), "PT round launch");
+    if (!rc) rc = check_hip(ctx, hipEventRecord(ctx->ev1, s), "event record");
+    if (rc) return rc;
+    record_stats(ctx, sh, rounds);
+
+    if (out) {
+        da_result o{out->best_x, out->best_E, out->final_x, out->final_E, out->n_accept};
+        rc = copy_outputs_to_host(ctx, J, R, &o, s);
+        hipError_t e = hipSuccess;
+        if (!rc && out->slot) e = hipMemcpy(out->slot, ctx->pt_lvl, (size_t)R * 4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && !rc && out->n_swaps)
+            e = hipMemcpy(out->n_swaps, ctx->pt_swaps, (size_t)chains * 8, hipMemcpyDeviceToHost);
+        if (!rc) rc = check_hip(ctx, e, "PT output copy");
+    } else {
+        rc = check_hip(ctx, hipStreamSynchronize(s), "stream synchronise");
+    }
+    return rc;
+}
+
+int da_energy(da_ctx *ctx, const uint8_t *x, int32_t count, int64_t *E) {
+    if (!ctx || !x || !E || count < 1) return fail(ctx, DA_EINVAL, "bad energy arguments");
+    const size_t ld = (size_t)ctx->ld, N = (size_t)ctx->N;
+    std::vector<uint8_t> xp((size_t)count * ld, 0);
+    for (size_t r = 0; r < (size_t)count; ++r)
+        for (size_t i = 0; i < N; ++i) xp[r * ld + i] = x[r * N + i] ? 1 : 0;
+    uint8_t *dX = nullptr;
+    int32_t *dH = nullptr;
+    int64_t *dE = nullptr;
+    hipStream_t s = ctx->own_stream;
+    int rc = check_hip(ctx, hipMalloc(&dX, xp.size()), "energy allocation");
+    if (!rc) rc = check_hip(ctx, hipMalloc(&dH, (size_t)count * ld * 4), "energy allocation");
+    if (!rc) rc = check_hip(ctx, hipMalloc(&dE, (size_t)count * 8), "energy allocation");
+    if (!rc) rc = check_hip(ctx, hipMemcpyAsync(dX, xp.data(), xp.size(), hipMemcpyHostToDevice, s), "energy upload");
+    JobDesc J{};
+    J.W = ctx->d_W;
+    J.b = ctx->d_b;
+    J.N = ctx->N;
+    J.ld = ctx->ld;
+    J.dtype = ctx->dtype;
+    J.wscale = ctx->wscale;
+    if (!rc) rc = check_hip(ctx, (hipError_t)launch_fields(J, dX, count, dH, s), "field launch");
+    if (!rc) rc = check_hip(ctx, (hipError_t)launch_energy_from_fields(J, dX, dH, count, dE, false, s), "energy launch");
+    if (!rc) rc = check_hip(ctx, hipMemcpyAsync(E, dE, (size_t)count * 8, hipMemcpyDeviceToHost, s), "energy copy");
+    if (!rc) rc = check_hip(ctx, hipStreamSynchronize(s), "stream synchronise");
+    if (dX) (void)hipFree(dX);
+    if (dH) (void)hipFree(dH);
+    if (dE) (void)hipFree(dE);
+    return rc;
+}
+
+int da_last_kernel_stats(da_ctx *ctx, da_kernel_stats *stats) {
+    if (!ctx || !stats) return fail(ctx, DA_EINVAL, "null argument");
+    if (!ctx->have_stats) return fail(ctx, DA_EINVAL, "no launch recorded yet");
+    int rc = check_hip(ctx, hipEventSynchronize(ctx->ev1), "event synchronise");
+    if (rc) return rc;
+    float ms = 0.f;
+    rc = check_hip(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1), "event elapsed time");
+    if (rc) return rc;
+    ctx->last.kernel_ms = ms;
+    *stats = ctx->last;
+    return DA_OK;
+}
+
+const char *da_last_error(const da_ctx *ctx) {
+    if (ctx) return ctx->err.c_str();
+    return t_err.c_str();
+}
+
+const char *da_strerror(int status) {
+    switch (status) {
+        case DA_OK: return "ok";
+        case DA_EINVAL: return "invalid argument";
+        case DA_ERANGE: return "coefficients out of range";
+        case DA_ENOMEM: return "out of memory";
+        case DA_EDEVICE: return "device error";
+        case DA_ENOTREADY: return "not ready";
+        case DA_ENOTFOUND: return "unknown ticket";
+        default: return "unknown status";
+    }
+}
+
+int da_threshold_table(double T, int32_t *thr) {
+    if (!thr) return fail(nullptr, DA_EINVAL, "thr is null");
+    build_threshold_table(T, thr);
+    return DA_OK;
+}
+
+double da_level_temperature(const da_schedule *schedule, int32_t level) {
+    if (!schedule) return NAN;
+    return schedule_temperature(*schedule, level);
+}
+
+}  // extern "C"

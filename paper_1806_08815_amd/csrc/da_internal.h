@@ -1,0 +1,107 @@
+// da_internal.h -- structures shared by the host runtime and the gfx950 kernels.
+//
+// Device data layout (all in HBM, one context per instance):
+//   W    [ld rows][ld] int8/int16/int32, row-major, symmetric, zero diagonal,
+//        zero padding beyond N; stores W / wscale.
+//   b    [ld] int32, zero beyond N.
+//   Replica state, [R] replicas, row stride ld:
+//     h [R][ld] int32 local fields, x / bx [R][ld] uint8 current / best state,
+//     E, bE, nacc [R] int64, eoff [R] int32.
+//   Level tables (one level per temperature in force):
+//     thr [L][65536] int32 Metropolis thresholds,
+//     hdr [L] LevelHdr, brk [...] uint32 acceptance brackets (see below).
+#pragma once
+
+#include <cstdint>
+
+namespace dapt {
+
+// The band of a level: with thr non-increasing in u, every d <= tmin = thr[65535]
+// is accepted for all draws and every d > tmax = thr[0] is rejected for all
+// draws, so only tmin < d <= tmax needs a random draw.  Inside the band the
+// accepting draws of d form a prefix u < ucut(d) = #{u : thr[u] >= d}, with
+// ucut non-increasing in d.  The band is cut into buckets of 2^sh values of d;
+// bucket D holds (lo, hi) = (ucut(last d of the bucket), ucut(first d)) packed
+// as lo | hi << 16, so u < lo accepts, u >= hi rejects, and only lo <= u < hi
+// needs the table entry thr[u].  With sh = 0 the bracket is exact (lo == hi).
+struct LevelHdr {
+    int32_t tmin;
+    int32_t tmax;
+    int32_t sh;
+    int32_t off;   // first bucket of this level in brk
+};
+
+constexpr int kMaxBuckets = 4096;   // buckets per level
+constexpr int kMaxLevels = 4096;
+constexpr int kMaxN = 8192;
+constexpr int32_t kEoffMax = 1 << 30;
+
+// One anneal segment (or one parallel-tempering round) of one instance.
+struct JobDesc {
+    const void *W;
+    const int32_t *b;
+    int32_t N, ld, dtype, wscale;
+    int32_t *h;
+    uint8_t *x;
+    uint8_t *bx;
+    int64_t *E;
+    int64_t *bE;
+    int32_t *eoff;
+    int64_t *nacc;
+    int32_t R;             // replicas of this job (state rows 0..R-1)
+    uint32_t rid_base;     // random-number replica id of state row 0
+    uint64_t seed;
+    int64_t s0, s1, S;     // run steps [s0, s1) of an S-step schedule
+    int32_t L;             // schedule levels (anneal mode)
+    int32_t eoff_inc;
+    const int32_t *lvl_of_rep;   // PT mode: level of each replica, else null
+    const uint32_t *round_ptr;   // PT mode: device round counter, else null
+    int32_t K;                   // PT mode: steps per round
+    int32_t NW;                  // waves per replica
+    int32_t RPW;                 // replicas per workgroup
+    int32_t w_lds;               // W staged in LDS
+    const LevelHdr *hdr;
+    const uint32_t *brk;
+    const int32_t *thr;
+};
+
+struct TraceDesc {
+    int32_t *k;
+    int64_t *E;
+    int64_t *eoff;
+    int64_t stride;        // steps per replica row
+};
+
+// Work item of the batched persistent kernel: `count` replica slots of job
+// `job` starting at state row `r0`.
+struct BatchItem {
+    int32_t job;
+    int32_t r0;
+};
+
+// Host-side launch wrappers implemented in da_kernels.hip.  All enqueue on
+// `stream` and return a hipError_t value as int.
+int launch_state_zero(const JobDesc &J, void *stream);
+int launch_rand_bits(uint8_t *X, int32_t R, int32_t N, int32_t ld, uint32_t rid_base,
+                     uint64_t seed, void *stream);
+int launch_fields(const JobDesc &J, const uint8_t *X, int32_t R, int32_t *H, void *stream);
+int launch_energy_from_fields(const JobDesc &J, const uint8_t *X, const int32_t *H, int32_t R,
+                              int64_t *E_out, bool finish_state, void *stream);
+int launch_run(const JobDesc &J, int F, const TraceDesc *trace, int blocks, int threads,
+               size_t lds_bytes, void *stream);
+int launch_batch(const JobDesc *jobs_dev, const BatchItem *items_dev, int n_items,
+                 int32_t *counter_dev, int blocks, int threads, size_t lds_bytes, void *stream);
+int launch_pt_exchange(int64_t *E, int32_t *slot2rep, int32_t *lvl_of_rep, const double *dbeta,
+                       const double *lnU, int32_t M, int32_t chains, uint64_t seed,
+                       uint32_t *round_ptr, int64_t *n_swaps, void *stream);
+int launch_pt_setup(int32_t *slot2rep, int32_t *lvl_of_rep, int64_t *n_swaps,
+                    uint32_t *round_ptr, int32_t M, int32_t chains, void *stream);
+int launch_extract(const JobDesc &J, const uint8_t *src_x, uint8_t *dst_x, int32_t R,
+                   void *stream);
+int launch_copy_i64(const int64_t *src, int64_t *dst, int32_t n, void *stream);
+int launch_fill_i32(int32_t *dst, int32_t value, int64_t n, void *stream);
+
+// Workgroup LDS bytes the run kernel needs for a launch shape.
+size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes);
+
+}  // namespace dapt

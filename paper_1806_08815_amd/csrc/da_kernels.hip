@@ -1,0 +1,767 @@
+// da_kernels.hip -- gfx950 kernels of the Digital Annealer parallel-trial step.
+//
+// Method: Algorithm 2 (Sec. II.B) of Aramon et al., arXiv:1806.08815, and its
+// parallel-tempering variant (Sec. II.D, exchange move of Algorithm 3).
+//
+// Mapping of one DA step onto CDNA4:
+//   * A replica is NW wavefronts; lane g of the replica owns the F consecutive
+//     variables i0 = g*F .. g*F+F-1 and keeps their fields h (int32) and bits
+//     of x in registers for the whole run.
+//   * Each lane scores its F flips, d = (1 - 2 x_i) h_i - E_offset.  The level's
+//     band decides most of them with no random draw: d <= tmin accepts,
+//     d > tmax rejects.  Only in-band flips pay for a Philox4x32-10 block (one
+//     block per 8 variables, so F <= 8 costs one call per lane) and an
+//     acceptance bracket; a global table read is needed only inside a
+//     non-exact bracket.  This reproduces d <= thr[u] exactly.
+//   * The accepted count and the rank of the chosen flip come from wave
+//     ballots of the bits of each lane's accepted count plus mbcnt (an
+//     exclusive prefix sum without data movement).  With NW > 1, lanes publish
+//     their masks, x bits and costs to LDS (double-buffered by step parity) and
+//     one workgroup barrier per step lets every wave find the chosen flip k on
+//     its own; nothing else is shared.
+//   * The only bulk traffic of a step is row k of W (N * dtype bytes), streamed
+//     once: every lane loads its F contiguous couplings with vector loads and
+//     updates its fields.  W stays in L2 / MALL / HBM, or in LDS when small.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "da_internal.h"
+
+namespace dapt {
+
+namespace {
+
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+enum : uint32_t { kTagMetropolis = 0, kTagSelect = 1, kTagExchange = 2, kTagInit = 3 };
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
+// with the key advanced by the Weyl constants between rounds.
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += kPhiloxW0;
+            k1 += kPhiloxW1;
+        }
+        const uint32_t hi0 = __umulhi(kPhiloxM0, c0);
+        const uint32_t lo0 = kPhiloxM0 * c0;
+        const uint32_t hi1 = __umulhi(kPhiloxM1, c2);
+        const uint32_t lo1 = kPhiloxM1 * c2;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ uint32_t word_of(const uint4 &v, int w) {
+    return w == 0 ? v.x : (w == 1 ? v.y : (w == 2 ? v.z : v.w));
+}
+
+// Number of set bits of `mask` in lanes below this one.
+__device__ __forceinline__ int mbcnt64(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ int readlane(int v, int lane) {
+    return __builtin_amdgcn_readlane(v, lane);
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Exclusive prefix sum over the wave of c (0 <= c < 32) and the wave total,
+// from ballots of the bits of c.
+template <int BITS>
+__device__ __forceinline__ void wave_prefix(int c, int &excl, int &total) {
+    excl = 0;
+    total = 0;
+#pragma unroll
+    for (int q = 0; q < BITS; ++q) {
+        const uint64_t bq = ballot((c >> q) & 1);
+        excl += mbcnt64(bq) << q;
+        total += __popcll(bq) << q;
+    }
+}
+
+// Position of the r-th (0-based) set bit of m.
+__device__ __forceinline__ int select_bit(uint32_t m, int r) {
+    for (int q = 0; q < r; ++q) m &= m - 1u;
+    return __ffs(m) - 1;
+}
+
+template <int F>
+struct CountBits {
+    static constexpr int value = (F >= 16) ? 5 : (F >= 8 ? 4 : (F >= 4 ? 3 : (F >= 2 ? 2 : 1)));
+};
+
+template <typename T, int F>
+struct VecOf {
+    typedef T type __attribute__((ext_vector_type(F)));
+};
+
+// Sign-extended load of F consecutive couplings.
+template <typename WT, int F>
+__device__ __forceinline__ void load_row(const WT *p, int (&w)[F]) {
+    typedef typename VecOf<WT, F>::type V;
+    const V v = *reinterpret_cast<const V *>(p);
+#pragma unroll
+    for (int f = 0; f < F; ++f) w[f] = (int)v[f];
+}
+
+// Level in force at step s of an S-step, L-level schedule: floor(s L / S).
+__device__ __forceinline__ int level_of(int64_t s, int32_t L, int64_t S) {
+    return S > 0 ? (int)((s * (int64_t)L) / S) : 0;
+}
+
+// First step whose level exceeds `lvl`.
+__device__ __forceinline__ int64_t next_level_step(int lvl, int32_t L, int64_t S) {
+    if (lvl + 1 >= L) return INT64_MAX;
+    return ((int64_t)(lvl + 1) * S + L - 1) / L;
+}
+
+}  // namespace
+
+size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes) {
+    size_t per_slot = 0;
+    if (NW > 1) per_slot = 2 * (size_t)NW * 4 + 2 * (size_t)NW * 64 * 4 + 2 * (size_t)NW * 64 * F * 4;
+    size_t w = (size_t)((w_lds_bytes + 15) & ~15);
+    return w + per_slot * RPW;
+}
+
+// Runs steps [s0, s1) for the replicas of one workgroup.  `blk` selects which
+// replicas of the job (rows blk*RPW ..).  All waves of the workgroup execute
+// the same number of loop iterations and barriers.
+template <typename WT, int F, bool TRACE>
+__device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *smem,
+                                          const TraceDesc &T) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int NW = J.NW;
+    const int slot = wave / NW;
+    const int wr = wave - slot * NW;
+    const int g = wr * 64 + lane;
+    const int i0 = g * F;
+    const int rr = blk * J.RPW + slot;
+    const bool active = (slot < J.RPW) && (rr < J.R);
+    const bool lane_has = active && (i0 < J.ld);
+    const uint32_t rid = J.rid_base + (uint32_t)rr;
+    const uint32_t k0 = (uint32_t)J.seed;
+    const uint32_t k1 = (uint32_t)(J.seed >> 32);
+    const int ld = J.ld;
+    const int wscale = J.wscale;
+
+    int64_t s0 = J.s0, s1 = J.s1;
+    if (J.round_ptr) {
+        const uint32_t t = *J.round_ptr;
+        s0 = (int64_t)t * J.K;
+        s1 = s0 + J.K;
+    }
+
+    // --- LDS carve-up ----------------------------------------------------
+    const int w_bytes = J.w_lds ? ((J.N * ld * (int)sizeof(WT) + 15) & ~15) : 0;
+    WT *Wl = reinterpret_cast<WT *>(smem);
+    uint8_t *sel = smem + w_bytes;
+    const size_t slot_bytes =
+        (NW > 1) ? (2 * (size_t)NW * 4 + 2 * (size_t)NW * 64 * 4 + 2 * (size_t)NW * 64 * F * 4) : 0;
+    int *tot = reinterpret_cast<int *>(sel + slot_bytes * slot);        // [2][NW]
+    uint32_t *rec = reinterpret_cast<uint32_t *>(tot + 2 * NW);        // [2][NW*64]
+    int *dv = reinterpret_cast<int *>(rec + 2 * NW * 64);               // [2][NW*64*F]
+
+    if (J.w_lds) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(J.W);
+        uint4 *dst = reinterpret_cast<uint4 *>(Wl);
+        const int n16 = (J.N * ld * (int)sizeof(WT)) / 16;
+        for (int q = threadIdx.x; q < n16; q += blockDim.x) dst[q] = src[q];
+        __syncthreads();
+    }
+
+    // --- replica state into registers --------------------------------------
+    int h[F];
+    uint32_t xb = 0, bxb = 0, vmask = 0;
+#pragma unroll
+    for (int f = 0; f < F; ++f) h[f] = 0;
+    if (lane_has) {
+        const size_t base = (size_t)rr * ld + i0;
+        typedef typename VecOf<int, F>::type IV;
+        typedef typename VecOf<uint8_t, F>::type BV;
+        const IV hv = *reinterpret_cast<const IV *>(J.h + base);
+        const BV xv = *reinterpret_cast<const BV *>(J.x + base);
+        const BV bv = *reinterpret_cast<const BV *>(J.bx + base);
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            h[f] = hv[f];
+            xb |= (uint32_t)(xv[f] & 1) << f;
+            bxb |= (uint32_t)(bv[f] & 1) << f;
+            if (i0 + f < J.N) vmask |= 1u << f;
+        }
+    }
+    int64_t E = 0, bE = 0, nacc = 0;
+    int32_t eoff = 0;
+    if (active) {
+        E = J.E[rr];
+        bE = J.bE[rr];
+        eoff = J.eoff[rr];
+        nacc = J.nacc[rr];
+    }
+
+    // --- level in force ----------------------------------------------------
+    int lvl;
+    int64_t s_next;
+    if (J.lvl_of_rep) {
+        lvl = active ? J.lvl_of_rep[rr] : 0;
+        s_next = INT64_MAX;
+    } else {
+        lvl = level_of(s0, J.L, J.S);
+        s_next = next_level_step(lvl, J.L, J.S);
+    }
+    LevelHdr hd = J.hdr[lvl];
+
+    for (int64_t s = s0; s < s1; ++s) {
+        if (s == s_next) {
+            lvl = level_of(s, J.L, J.S);
+            s_next = next_level_step(lvl, J.L, J.S);
+            hd = J.hdr[lvl];
+        }
+        const int par = (int)(s & 1);
+
+        // 1. cost of every flip and the draw-free decisions
+        int d[F];
+        uint32_t acc = 0, inb = 0;
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            const int dd = (((xb >> f) & 1u) ? -h[f] : h[f]) - eoff;
+            d[f] = dd;
+            const bool v = (vmask >> f) & 1u;
+            if (v && dd <= hd.tmin) acc |= 1u << f;
+            else if (v && dd <= hd.tmax) inb |= 1u << f;
+        }
+
+        // 2. in-band flips: Philox draw and bracket (table only when needed)
+        if (inb) {
+            uint4 rb[(F + 7) / 8];
+#pragma unroll
+            for (int q = 0; q < (F + 7) / 8; ++q)
+                rb[q] = philox((uint32_t)(i0 >> 3) + q, (uint32_t)s, rid, kTagMetropolis, k0, k1);
+            const uint32_t *brk = J.brk + hd.off;
+            const int32_t *thr = J.thr + (size_t)lvl * 65536;
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                if (!((inb >> f) & 1u)) continue;
+                const int slice = (F >= 8) ? (f & 7) : ((i0 & 7) + f);
+                const uint32_t wv = word_of(rb[f >> 3], slice >> 1);
+                const uint32_t u = (slice & 1) ? (wv >> 16) : (wv & 0xFFFFu);
+                const uint32_t e = brk[(d[f] - hd.tmin - 1) >> hd.sh];
+                const uint32_t lo = e & 0xFFFFu, hi = e >> 16;
+                bool a = u < lo;
+                if (!a && u < hi) a = d[f] <= thr[u];
+                if (a) acc |= 1u << f;
+            }
+        }
+
+        // 3. accepted count and the chosen flip
+        const int c = __popc(acc);
+        int excl, wtot;
+        wave_prefix<CountBits<F>::value>(c, excl, wtot);
+
+        int m, k, xk, dk;
+        if (NW == 1) {
+            m = wtot;
+            if (m == 0) {
+                eoff = min(eoff + J.eoff_inc, kEoffMax);
+                if (TRACE && active && g == 0) {
+                    T.k[rr * T.stride + (s - s0)] = -1;
+                    T.E[rr * T.stride + (s - s0)] = E;
+                    T.eoff[rr * T.stride + (s - s0)] = eoff;
+                }
+                continue;
+            }
+            const uint32_t v = philox(0u, (uint32_t)s, rid, kTagSelect, k0, k1).x;
+            const int j = (int)(((uint64_t)v * (uint32_t)m) >> 32);
+            const int incl = excl + c;
+            const uint64_t bal = ballot(incl > j);
+            const int ts = __ffsll((unsigned long long)bal) - 1;
+            const int rloc = j - readlane(excl, ts);
+            const uint32_t msk = (uint32_t)readlane((int)acc, ts);
+            const int bit = select_bit(msk, rloc);
+            int dsel = d[0];
+#pragma unroll
+            for (int f = 1; f < F; ++f) dsel = (bit == f) ? d[f] : dsel;
+            k = ts * F + bit;
+            xk = (readlane((int)xb, ts) >> bit) & 1;
+            dk = readlane(dsel, ts);
+        } else {
+            // publish this wave's lanes, then one barrier
+            rec[par * NW * 64 + g] = acc | (xb << 16);
+#pragma unroll
+            for (int f = 0; f < F; ++f) dv[(par * NW * 64 + g) * F + f] = d[f];
+            if (lane == 0) tot[par * NW + wr] = wtot;
+            __syncthreads();
+            const int tw = (lane < NW) ? tot[par * NW + lane] : 0;
+            int scan = tw;
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) {
+                const int t = __shfl_up(scan, o, 64);
+                if (lane >= o) scan += t;
+            }
+            m = readlane(scan, NW - 1);
+            if (m == 0) {
+                eoff = min(eoff + J.eoff_inc, kEoffMax);
+                if (TRACE && active && g == 0) {
+                    T.k[rr * T.stride + (s - s0)] = -1;
+                    T.E[rr * T.stride + (s - s0)] = E;
+                    T.eoff[rr * T.stride + (s - s0)] = eoff;
+                }
+                continue;
+            }
+            const uint32_t v = philox(0u, (uint32_t)s, rid, kTagSelect, k0, k1).x;
+            const int j = (int)(((uint64_t)v * (uint32_t)m) >> 32);
+            const uint64_t wbal = ballot(lane < NW && scan > j);
+            const int ws = __ffsll((unsigned long long)wbal) - 1;
+            const int jw = j - (readlane(scan, ws) - readlane(tw, ws));
+            const uint32_t r2 = rec[par * NW * 64 + ws * 64 + lane];
+            const int c2 = __popc(r2 & 0xFFFFu);
+            int excl2, tot2;
+            wave_prefix<CountBits<F>::value>(c2, excl2, tot2);
+            const uint64_t bal = ballot(excl2 + c2 > jw);
+            const int ts = __ffsll((unsigned long long)bal) - 1;
+            const int rloc = jw - readlane(excl2, ts);
+            const uint32_t rs = (uint32_t)readlane((int)r2, ts);
+            const int bit = select_bit(rs & 0xFFFFu, rloc);
+            const int gk = ws * 64 + ts;
+            k = gk * F + bit;
+            xk = (rs >> (16 + bit)) & 1;
+            dk = dv[(par * NW * 64 + gk) * F + bit];
+        }
+
+        // 4. apply the flip: energy, state, every field from row k of W
+        E += (int64_t)dk + eoff;
+        const int delta = xk ? -1 : 1;
+        if (g == (k / F)) xb ^= 1u << (k % F);
+        if (lane_has) {
+            int w[F];
+            if (J.w_lds) {
+#pragma unroll
+                for (int f = 0; f < F; ++f) w[f] = (int)Wl[(size_t)k * ld + i0 + f];
+            } else {
+                load_row<WT, F>(reinterpret_cast<const WT *>(J.W) + (size_t)k * ld + i0, w);
+            }
+            if (wscale == 1) {
+#pragma unroll
+                for (int f = 0; f < F; ++f) h[f] += delta > 0 ? w[f] : -w[f];
+            } else {
+#pragma unroll
+                for (int f = 0; f < F; ++f) h[f] += delta * (w[f] * wscale);
+            }
+        }
+        eoff = 0;
+        ++nacc;
+        if (E < bE) {
+            bE = E;
+            bxb = xb;
+        }
+        if (TRACE && active && g == 0) {
+            T.k[rr * T.stride + (s - s0)] = k;
+            T.E[rr * T.stride + (s - s0)] = E;
+            T.eoff[rr * T.stride + (s - s0)] = eoff;
+        }
+    }
+
+    // --- state back to HBM -------------------------------------------------
+    if (lane_has) {
+        const size_t base = (size_t)rr * ld + i0;
+        typedef typename VecOf<int, F>::type IV;
+        typedef typename VecOf<uint8_t, F>::type BV;
+        IV hv;
+        BV xv, bv;
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            hv[f] = h[f];
+            xv[f] = (uint8_t)((xb >> f) & 1u);
+            bv[f] = (uint8_t)((bxb >> f) & 1u);
+        }
+        *reinterpret_cast<IV *>(J.h + base) = hv;
+        *reinterpret_cast<BV *>(J.x + base) = xv;
+        *reinterpret_cast<BV *>(J.bx + base) = bv;
+    }
+    if (active && g == 0) {
+        J.E[rr] = E;
+        J.bE[rr] = bE;
+        J.eoff[rr] = eoff;
+        J.nacc[rr] = nacc;
+    }
+}
+
+template <typename WT, int F, bool TRACE>
+__global__ __launch_bounds__(1024) void k_run(JobDesc J, TraceDesc T) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    run_block<WT, F, TRACE>(J, blockIdx.x, smem, T);
+}
+
+// Persistent batched form: workgroups pull (job, replica-block) items from a
+// device counter until none are left.  Every item of a launch uses the
+// launch's workgroup size; jobs of any size and coupling type mix freely.
+template <int F>
+__global__ __launch_bounds__(1024) void k_batch(const JobDesc *__restrict__ jobs,
+                                                const BatchItem *__restrict__ items, int n_items,
+                                                int32_t *counter) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ int item_id;
+    const TraceDesc T{nullptr, nullptr, nullptr, 0};
+    for (;;) {
+        if (threadIdx.x == 0) item_id = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = item_id;
+        __syncthreads();
+        if (it >= n_items) break;
+        const BatchItem bi = items[it];
+        JobDesc J = jobs[bi.job];
+        const int blk = bi.r0 / J.RPW;
+        if (J.dtype == 1) run_block<int8_t, F, false>(J, blk, smem, T);
+        else if (J.dtype == 2) run_block<int16_t, F, false>(J, blk, smem, T);
+        else run_block<int32_t, F, false>(J, blk, smem, T);
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------------------------
+// Initial states.
+// --------------------------------------------------------------------------
+
+// Common all-zero start: x = 0, h = b, E = 0 (Algorithm 2 runs all start from
+// the same state, which spares computing fields and energies per run).
+__global__ void k_state_zero(JobDesc J) {
+    const int64_t n = (int64_t)J.R * J.ld;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(q % J.ld);
+        J.h[q] = J.b[i];
+        J.x[q] = 0;
+        J.bx[q] = 0;
+        if (i == 0) {
+            const int64_t r = q / J.ld;
+            J.E[r] = 0;
+            J.bE[r] = 0;
+            J.eoff[r] = 0;
+            J.nacc[r] = 0;
+        }
+    }
+}
+
+// Random start: bit i of replica id rid_base + r is bit (i & 31) of word
+// (i >> 5) & 3 of Philox(i >> 7, 0, rid, init tag).
+__global__ void k_rand_bits(uint8_t *X, int32_t R, int32_t N, int32_t ld, uint32_t rid_base,
+                            uint64_t seed) {
+    const int64_t n = (int64_t)R * ld;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(q % ld);
+        const uint32_t r = (uint32_t)(q / ld);
+        uint8_t bit = 0;
+        if (i < N) {
+            const uint4 w = philox((uint32_t)i >> 7, 0u, rid_base + r, kTagInit, k0, k1);
+            bit = (uint8_t)((word_of(w, (i >> 5) & 3) >> (i & 31)) & 1u);
+        }
+        X[q] = bit;
+    }
+}
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+// Initial fields H = X W^T + b for int8 couplings on the matrix cores:
+// v_mfma_i32_32x32x32_i8, exact int8 x int8 -> int32.  One wave per 32 x 32
+// output tile (32 replicas x 32 variables); both operands are read with the
+// reduction index contiguous (rows of X and rows of the symmetric W).
+__global__ __launch_bounds__(256) void k_fields_mfma_i8(const uint8_t *__restrict__ X,
+                                                        const int8_t *__restrict__ W,
+                                                        const int32_t *__restrict__ b,
+                                                        int32_t *__restrict__ H, int32_t R,
+                                                        int32_t ld, int32_t wscale) {
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int tiles_i = ld / 32;
+    const int tr = wave / tiles_i, ti = wave - tr * tiles_i;
+    const int r0 = tr * 32, c0 = ti * 32;
+    if (r0 >= R) return;
+    const int row = lane & 31, kh = (lane >> 5) * 16;
+    const int ra = min(r0 + row, R - 1);
+    const int8_t *pa = reinterpret_cast<const int8_t *>(X) + (size_t)ra * ld + kh;
+    const int8_t *pb = W + (size_t)(c0 + row) * ld + kh;
+    v16i acc = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int kk = 0; kk < ld; kk += 32) {
+        const v4i a = *reinterpret_cast<const v4i *>(pa + kk);
+        const v4i bb = *reinterpret_cast<const v4i *>(pb + kk);
+        acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, bb, acc, 0, 0, 0);
+    }
+    const int col = c0 + (lane & 31);
+    const int bcol = b[col];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int r = r0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        if (r < R) H[(size_t)r * ld + col] = acc[v] * wscale + bcol;
+    }
+}
+
+// Initial fields for int16 / int32 couplings: one workgroup per replica adds
+// row j of W for every set bit x_j (rows are coalesced across the workgroup).
+template <typename WT>
+__global__ __launch_bounds__(256) void k_fields_rows(const uint8_t *__restrict__ X,
+                                                     const WT *__restrict__ W,
+                                                     const int32_t *__restrict__ b,
+                                                     int32_t *__restrict__ H, int32_t N,
+                                                     int32_t ld, int32_t wscale) {
+    const int r = blockIdx.x;
+    const uint8_t *xr = X + (size_t)r * ld;
+    for (int i0 = 0; i0 < ld; i0 += blockDim.x) {
+        const int i = i0 + threadIdx.x;
+        int acc = 0;
+        for (int j = 0; j < N; ++j)
+            if (xr[j]) acc += (i < ld ? (int)W[(size_t)j * ld + i] : 0);
+        if (i < ld) H[(size_t)r * ld + i] = acc * wscale + b[i];
+    }
+}
+
+// E = b.x + (1/2) x.(h - b) = (1/2) sum_i x_i (h_i + b_i), exact in int64.
+// With finish_state the replica state is completed (x copied to best, offsets
+// and counters cleared); otherwise only E_out is written.
+__global__ __launch_bounds__(256) void k_energy_from_fields(const uint8_t *__restrict__ X,
+                                                            const int32_t *__restrict__ H,
+                                                            const int32_t *__restrict__ b,
+                                                            int32_t ld, int64_t *E_out,
+                                                            int finish, uint8_t *bx,
+                                                            int64_t *bE, int32_t *eoff,
+                                                            int64_t *nacc) {
+    __shared__ long long part[256];
+    const int r = blockIdx.x;
+    long long acc = 0;
+    for (int i = threadIdx.x; i < ld; i += blockDim.x) {
+        const size_t q = (size_t)r * ld + i;
+        if (X[q]) acc += (long long)H[q] + b[i];
+        if (finish) bx[q] = X[q];
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const long long e = part[0] / 2;
+        E_out[r] = e;
+        if (finish) {
+            bE[r] = e;
+            eoff[r] = 0;
+            nacc[r] = 0;
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Parallel tempering: replica exchange on the device (Algorithm 3's exchange
+// move; Sec. II.D notes the next DA generation moves it off the host).
+// slot2rep[c*M + p] is the replica (0..M-1) at temperature p of chain c.
+// --------------------------------------------------------------------------
+__global__ void k_pt_exchange(const int64_t *__restrict__ E, int32_t *slot2rep,
+                              int32_t *lvl_of_rep, const double *__restrict__ dbeta,
+                              const double *__restrict__ lnU, int32_t M, int32_t chains,
+                              uint64_t seed, uint32_t *round_ptr, int64_t *n_swaps) {
+    const uint32_t t = *round_ptr;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    for (int c = threadIdx.x; c < chains; c += blockDim.x) {
+        int32_t *s2r = slot2rep + (size_t)c * M;
+        int64_t sw = 0;
+        for (int p = 0; p + 1 < M; ++p) {
+            const int a = s2r[p], bq = s2r[p + 1];
+            const double diff = (double)(E[(size_t)c * M + a] - E[(size_t)c * M + bq]);
+            const double delta = __dmul_rn(dbeta[p], diff);
+            const uint32_t u = philox((uint32_t)p, t, (uint32_t)c, kTagExchange, k0, k1).x & 0xFFFFu;
+            if (lnU[u] < delta) {
+                s2r[p] = bq;
+                s2r[p + 1] = a;
+                ++sw;
+            }
+        }
+        n_swaps[c] += sw;
+        for (int p = 0; p < M; ++p) lvl_of_rep[(size_t)c * M + s2r[p]] = p;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *round_ptr = t + 1;
+}
+
+__global__ void k_pt_setup(int32_t *slot2rep, int32_t *lvl_of_rep, int64_t *n_swaps,
+                           uint32_t *round_ptr, int32_t M, int32_t chains) {
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < M * chains;
+         q += gridDim.x * blockDim.x) {
+        slot2rep[q] = q % M;
+        lvl_of_rep[q] = q % M;
+        if (q < chains) n_swaps[q] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *round_ptr = 0;
+}
+
+// Copy [R][ld] state rows to dense [R][N] output rows.
+__global__ void k_extract(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst, int32_t R,
+                          int32_t N, int32_t ld) {
+    const int64_t n = (int64_t)R * N;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = q / N, i = q - r * N;
+        dst[q] = src[r * ld + i];
+    }
+}
+
+__global__ void k_copy_i64(const int64_t *__restrict__ src, int64_t *__restrict__ dst, int32_t n) {
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x)
+        dst[q] = src[q];
+}
+
+__global__ void k_fill_i32(int32_t *dst, int32_t value, int64_t n) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x)
+        dst[q] = value;
+}
+
+// --------------------------------------------------------------------------
+// Host launch wrappers.
+// --------------------------------------------------------------------------
+namespace {
+inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+inline int grid_for(int64_t n, int threads) {
+    int64_t g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > 65535) g = 65535;
+    return (int)g;
+}
+
+template <typename WT, int F, bool TRACE>
+int launch_run_t(const JobDesc &J, const TraceDesc &T, int blocks, int threads, size_t lds,
+                 void *stream) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_run<WT, F, TRACE>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_run<WT, F, TRACE>), dim3(blocks), dim3(threads), lds, S(stream), J, T);
+    return (int)hipGetLastError();
+}
+
+template <typename WT, bool TRACE>
+int launch_run_f(const JobDesc &J, int F, const TraceDesc &T, int blocks, int threads, size_t lds,
+                 void *stream) {
+    switch (F) {
+        case 4: return launch_run_t<WT, 4, TRACE>(J, T, blocks, threads, lds, stream);
+        case 8: return launch_run_t<WT, 8, TRACE>(J, T, blocks, threads, lds, stream);
+        case 16: return launch_run_t<WT, 16, TRACE>(J, T, blocks, threads, lds, stream);
+        default: return (int)hipErrorInvalidValue;
+    }
+}
+}  // namespace
+
+int launch_run(const JobDesc &J, int F, const TraceDesc *trace, int blocks, int threads,
+               size_t lds_bytes, void *stream) {
+    const TraceDesc none{nullptr, nullptr, nullptr, 0};
+    const bool tr = trace != nullptr;
+    const TraceDesc &T = tr ? *trace : none;
+    switch (J.dtype) {
+        case 1: return tr ? launch_run_f<int8_t, true>(J, F, T, blocks, threads, lds_bytes, stream)
+                          : launch_run_f<int8_t, false>(J, F, T, blocks, threads, lds_bytes, stream);
+        case 2: return tr ? launch_run_f<int16_t, true>(J, F, T, blocks, threads, lds_bytes, stream)
+                          : launch_run_f<int16_t, false>(J, F, T, blocks, threads, lds_bytes, stream);
+        case 4: return tr ? launch_run_f<int32_t, true>(J, F, T, blocks, threads, lds_bytes, stream)
+                          : launch_run_f<int32_t, false>(J, F, T, blocks, threads, lds_bytes, stream);
+        default: return (int)hipErrorInvalidValue;
+    }
+}
+
+int launch_batch(const JobDesc *jobs_dev, const BatchItem *items_dev, int n_items,
+                 int32_t *counter_dev, int blocks, int threads, size_t lds_bytes, void *stream) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch<8>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_batch<8>), dim3(blocks), dim3(threads), lds_bytes, S(stream), jobs_dev,
+                       items_dev, n_items, counter_dev);
+    return (int)hipGetLastError();
+}
+
+int launch_state_zero(const JobDesc &J, void *stream) {
+    hipLaunchKernelGGL(k_state_zero, dim3(grid_for((int64_t)J.R * J.ld, 256)), dim3(256), 0,
+                       S(stream), J);
+    return (int)hipGetLastError();
+}
+
+int launch_rand_bits(uint8_t *X, int32_t R, int32_t N, int32_t ld, uint32_t rid_base,
+                     uint64_t seed, void *stream) {
+    hipLaunchKernelGGL(k_rand_bits, dim3(grid_for((int64_t)R * ld, 256)), dim3(256), 0, S(stream),
+                       X, R, N, ld, rid_base, seed);
+    return (int)hipGetLastError();
+}
+
+int launch_fields(const JobDesc &J, const uint8_t *X, int32_t R, int32_t *H, void *stream) {
+    if (J.dtype == 1) {
+        const int waves = ((R + 31) / 32) * (J.ld / 32);
+        hipLaunchKernelGGL(k_fields_mfma_i8, dim3((waves + 3) / 4), dim3(256), 0, S(stream), X,
+                           reinterpret_cast<const int8_t *>(J.W), J.b, H, R, J.ld, J.wscale);
+    } else if (J.dtype == 2) {
+        hipLaunchKernelGGL(k_fields_rows<int16_t>, dim3(R), dim3(256), 0, S(stream), X,
+                           reinterpret_cast<const int16_t *>(J.W), J.b, H, J.N, J.ld, J.wscale);
+    } else {
+        hipLaunchKernelGGL(k_fields_rows<int32_t>, dim3(R), dim3(256), 0, S(stream), X,
+                           reinterpret_cast<const int32_t *>(J.W), J.b, H, J.N, J.ld, J.wscale);
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_energy_from_fields(const JobDesc &J, const uint8_t *X, const int32_t *H, int32_t R,
+                              int64_t *E_out, bool finish_state, void *stream) {
+    hipLaunchKernelGGL(k_energy_from_fields, dim3(R), dim3(256), 0, S(stream), X, H, J.b, J.ld,
+                       E_out, finish_state ? 1 : 0, J.bx, J.bE, J.eoff, J.nacc);
+    return (int)hipGetLastError();
+}
+
+int launch_pt_exchange(int64_t *E, int32_t *slot2rep, int32_t *lvl_of_rep, const double *dbeta,
+                       const double *lnU, int32_t M, int32_t chains, uint64_t seed,
+                       uint32_t *round_ptr, int64_t *n_swaps, void *stream) {
+    int threads = chains < 64 ? 64 : (chains > 1024 ? 1024 : ((chains + 63) / 64) * 64);
+    hipLaunchKernelGGL(k_pt_exchange, dim3(1), dim3(threads), 0, S(stream), E, slot2rep,
+                       lvl_of_rep, dbeta, lnU, M, chains, seed, round_ptr, n_swaps);
+    return (int)hipGetLastError();
+}
+
+int launch_pt_setup(int32_t *slot2rep, int32_t *lvl_of_rep, int64_t *n_swaps,
+                    uint32_t *round_ptr, int32_t M, int32_t chains, void *stream) {
+    hipLaunchKernelGGL(k_pt_setup, dim3(grid_for((int64_t)M * chains, 256)), dim3(256), 0,
+                       S(stream), slot2rep, lvl_of_rep, n_swaps, round_ptr, M, chains);
+    return (int)hipGetLastError();
+}
+
+int launch_extract(const JobDesc &J, const uint8_t *src_x, uint8_t *dst_x, int32_t R,
+                   void *stream) {
+    hipLaunchKernelGGL(k_extract, dim3(grid_for((int64_t)R * J.N, 256)), dim3(256), 0, S(stream),
+                       src_x, dst_x, R, J.N, J.ld);
+    return (int)hipGetLastError();
+}
+
+int launch_copy_i64(const int64_t *src, int64_t *dst, int32_t n, void *stream) {
+    hipLaunchKernelGGL(k_copy_i64, dim3(grid_for(n, 256)), dim3(256), 0, S(stream), src, dst, n);
+    return (int)hipGetLastError();
+}
+
+int launch_fill_i32(int32_t *dst, int32_t value, int64_t n, void *stream) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256)), dim3(256), 0, S(stream), dst, value, n);
+    return (int)hipGetLastError();
+}
+
+}  // namespace dapt

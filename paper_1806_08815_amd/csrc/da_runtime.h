@@ -1,0 +1,109 @@
+// da_runtime.h -- host runtime objects behind the C ABI of include/da.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "da.h"
+#include "da_internal.h"
+
+namespace dapt {
+
+// Device-resident Metropolis tables for a list of temperatures (one level per
+// temperature), shared by every context on the device through a cache.
+struct LevelTables {
+    std::vector<double> temps;
+    int32_t L = 0;
+    int32_t *d_thr = nullptr;      // [L][65536]
+    LevelHdr *d_hdr = nullptr;     // [L]
+    uint32_t *d_brk = nullptr;     // brackets of all levels
+    size_t bytes = 0;
+    std::vector<LevelHdr> hdr;     // host copy (tests, footprints)
+    ~LevelTables();
+};
+
+// Threshold table of one temperature (host): thr[u] = ceil(-T ln U_u) - 1,
+// U_u = (u + 1/2) / 65536, clamped to [-1, 2^30]; all -1 for T <= 0.
+void build_threshold_table(double T, int32_t *thr);
+// Band header and brackets of one level from its threshold table.
+void build_brackets(const int32_t *thr, LevelHdr &hd, std::vector<uint32_t> &brk);
+// Temperature of level l of a schedule.
+double schedule_temperature(const da_schedule &s, int l);
+// Tables for a temperature list (cached per device); nullptr on failure with
+// `err` set.
+std::shared_ptr<LevelTables> get_level_tables(const std::vector<double> &temps, std::string &err);
+// Device bytes of the tables of L levels with `buckets` brackets in total.
+int64_t level_table_bytes(int32_t L, int64_t buckets);
+
+// Replica state of one context ([cap] replicas of row stride ld).
+struct StateBuf {
+    int32_t *h = nullptr;
+    uint8_t *x = nullptr;
+    uint8_t *bx = nullptr;
+    int64_t *E = nullptr;
+    int64_t *bE = nullptr;
+    int32_t *eoff = nullptr;
+    int64_t *nacc = nullptr;
+    int32_t cap = 0;
+    int32_t ld = 0;
+    void release();
+    bool ensure(int32_t R, int32_t ld_, std::string &err);
+    int64_t bytes() const;
+    static int64_t bytes_for(int32_t R, int32_t ld);
+};
+
+// Launch shape of the step kernel.
+struct LaunchShape {
+    int F = 8;
+    int NW = 1;
+    int RPW = 1;
+    int w_lds = 0;
+    int threads = 64;
+    int blocks = 1;
+    size_t lds = 0;
+};
+
+}  // namespace dapt
+
+struct da_ctx {
+    int32_t N = 0;
+    int32_t ld = 0;
+    int32_t dtype = 0;     // bytes per stored coupling
+    int32_t wscale = 1;
+    int device = 0;
+    void *d_W = nullptr;
+    int32_t *d_b = nullptr;
+    dapt::StateBuf st;
+    hipStream_t own_stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    da_kernel_stats last{};
+    bool have_stats = false;
+    std::string err;
+    // PT scratch
+    int32_t *pt_slot2rep = nullptr, *pt_lvl = nullptr;
+    int64_t *pt_swaps = nullptr;
+    uint32_t *pt_round = nullptr;
+    double *pt_dbeta = nullptr, *pt_lnU = nullptr;
+    int32_t pt_cap_R = 0, pt_cap_M = 0, pt_cap_chains = 0;
+    std::shared_ptr<dapt::LevelTables> keep_tables;
+};
+
+namespace dapt {
+
+// Shared by da_api.cpp and da_server.cpp.
+void set_thread_error(const std::string &msg);
+int fail(da_ctx *ctx, int code, const std::string &msg);
+int check_hip(da_ctx *ctx, hipError_t e, const char *what);
+int validate_schedule(const da_schedule *s, std::string &err);
+LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch);
+JobDesc make_job(const da_ctx *ctx, const LevelTables &lt, int32_t R, uint32_t rid_base,
+                 uint64_t seed, int64_t steps, const da_schedule &s, const LaunchShape &sh);
+int init_state(da_ctx *ctx, const JobDesc &J, int init, hipStream_t stream);
+std::vector<double> schedule_temps(const da_schedule &s);
+
+}  // namespace dapt

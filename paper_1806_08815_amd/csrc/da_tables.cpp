@@ -1,0 +1,149 @@
+// da_tables.cpp -- temperature levels and the Metropolis decision tables.
+//
+// The Metropolis acceptance exp(-dE/T) (Sec. III of arXiv:1806.08815) is
+// decided in integers.  A 16-bit draw u stands for U_u = (u + 1/2)/65536, and a
+// flip of offset-shifted cost d is accepted iff U_u < exp(-d/T), which for an
+// integer d is d <= thr[u] with thr[u] = ceil(-T ln U_u) - 1.  The device
+// never evaluates a logarithm: it compares against these host-built tables,
+// so the decision is bit-identical wherever it is made.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "da_runtime.h"
+
+namespace dapt {
+
+namespace {
+constexpr int64_t kThrMax = int64_t(1) << 30;
+}
+
+void build_threshold_table(double T, int32_t *thr) {
+    for (int u = 0; u < 65536; ++u) {
+        if (!(T > 0.0)) {
+            thr[u] = -1;
+            continue;
+        }
+        const double U = ((double)u + 0.5) / 65536.0;
+        const double y = -T * std::log(U);
+        const double c = std::ceil(y) - 1.0;
+        int64_t t = (c >= (double)kThrMax) ? kThrMax : (int64_t)c;
+        if (t < -1) t = -1;
+        thr[u] = (int32_t)t;
+    }
+}
+
+// Number of draws accepting cost d: thr is non-increasing in u, so the
+// accepting draws form the prefix [0, ucut(d)).
+static int ucut(const int32_t *thr, int64_t d) {
+    int lo = 0, hi = 65536;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int64_t)thr[mid] >= d) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+void build_brackets(const int32_t *thr, LevelHdr &hd, std::vector<uint32_t> &brk) {
+    hd.tmin = thr[65535];
+    hd.tmax = thr[0];
+    hd.sh = 0;
+    hd.off = (int32_t)brk.size();
+    if (hd.tmax <= hd.tmin) return;   // no draw ever changes a decision
+    const int64_t range = (int64_t)hd.tmax - hd.tmin;
+    int sh = 0;
+    while (((range + (int64_t(1) << sh) - 1) >> sh) > kMaxBuckets) ++sh;
+    const int64_t nb = (range + (int64_t(1) << sh) - 1) >> sh;
+    for (int64_t D = 0; D < nb; ++D) {
+        const int64_t ds = (int64_t)hd.tmin + 1 + (D << sh);
+        int64_t de = ds + (int64_t(1) << sh) - 1;
+        if (de > hd.tmax) de = hd.tmax;
+        const uint32_t lo = (uint32_t)ucut(thr, de);
+        const uint32_t hi = (uint32_t)ucut(thr, ds);
+        brk.push_back(lo | (hi << 16));
+    }
+    hd.sh = sh;
+}
+
+double schedule_temperature(const da_schedule &s, int l) {
+    if (s.n_levels <= 1) return s.T_hi;
+    const double frac = (double)l / (double)(s.n_levels - 1);
+    if (s.kind == DA_SCHED_LINEAR_BETA)
+        return 1.0 / (1.0 / s.T_hi + (1.0 / s.T_lo - 1.0 / s.T_hi) * frac);
+    return s.T_hi * std::pow(s.T_lo / s.T_hi, frac);
+}
+
+std::vector<double> schedule_temps(const da_schedule &s) {
+    std::vector<double> t((size_t)s.n_levels);
+    for (int l = 0; l < s.n_levels; ++l) t[(size_t)l] = schedule_temperature(s, l);
+    return t;
+}
+
+int64_t level_table_bytes(int32_t L, int64_t buckets) {
+    return (int64_t)L * 65536 * 4 + (int64_t)L * (int64_t)sizeof(LevelHdr) + buckets * 4;
+}
+
+LevelTables::~LevelTables() {
+    if (d_thr) (void)hipFree(d_thr);
+    if (d_hdr) (void)hipFree(d_hdr);
+    if (d_brk) (void)hipFree(d_brk);
+}
+
+namespace {
+struct CacheKey {
+    int device;
+    std::string bits;
+    bool operator<(const CacheKey &o) const {
+        return device != o.device ? device < o.device : bits < o.bits;
+    }
+};
+std::mutex g_cache_mu;
+std::map<CacheKey, std::weak_ptr<LevelTables>> g_cache;
+}  // namespace
+
+std::shared_ptr<LevelTables> get_level_tables(const std::vector<double> &temps, std::string &err) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        err = "hipGetDevice failed";
+        return nullptr;
+    }
+    CacheKey key{dev, std::string(reinterpret_cast<const char *>(temps.data()),
+                                  temps.size() * sizeof(double))};
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+        if (auto sp = it->second.lock()) return sp;
+    }
+    auto lt = std::make_shared<LevelTables>();
+    lt->temps = temps;
+    lt->L = (int32_t)temps.size();
+    std::vector<int32_t> thr((size_t)lt->L * 65536);
+    std::vector<uint32_t> brk;
+    lt->hdr.resize((size_t)lt->L);
+    for (int l = 0; l < lt->L; ++l) {
+        build_threshold_table(temps[(size_t)l], thr.data() + (size_t)l * 65536);
+        build_brackets(thr.data() + (size_t)l * 65536, lt->hdr[(size_t)l], brk);
+    }
+    if (brk.empty()) brk.push_back(0);
+    const size_t thr_b = thr.size() * 4, hdr_b = lt->hdr.size() * sizeof(LevelHdr),
+                 brk_b = brk.size() * 4;
+    if (hipMalloc(&lt->d_thr, thr_b) != hipSuccess || hipMalloc(&lt->d_hdr, hdr_b) != hipSuccess ||
+        hipMalloc(&lt->d_brk, brk_b) != hipSuccess) {
+        err = "out of device memory for level tables";
+        return nullptr;
+    }
+    if (hipMemcpy(lt->d_thr, thr.data(), thr_b, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(lt->d_hdr, lt->hdr.data(), hdr_b, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(lt->d_brk, brk.data(), brk_b, hipMemcpyHostToDevice) != hipSuccess) {
+        err = "upload of level tables failed";
+        return nullptr;
+    }
+    lt->bytes = thr_b + hdr_b + brk_b;
+    g_cache[key] = lt;
+    return lt;
+}
+
+}  // namespace dapt

@@ -1,0 +1,155 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Everything here is integer work, so the bar is bit-exact: per-step traces
+(flipped variable, energy, offset), final and best states and energies, and
+accepted-step counts.  Cases span several tiles and ragged tails (N not a
+multiple of 8 or 64, replica counts not a multiple of the workgroup shape),
+every coupling storage type, every launch shape, zero and random starts,
+both schedule kinds, zero temperature and the offset ceiling.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1806_08815_amd import instances
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("best_x", "best_E", "final_x", "final_E", "n_accept")
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_1806_08815_amd import api as a
+    a.lib()
+    return a
+
+
+def _same(gpu, ref, keys=KEYS, rows=None):
+    for k in keys:
+        g = gpu[k] if rows is None else gpu[k][rows]
+        if not np.array_equal(g, ref[k]):
+            bad = np.argwhere(np.asarray(g) != np.asarray(ref[k]))[:5]
+            raise AssertionError(f"{k} differs at {bad.tolist()}")
+
+
+def _q(kind, N, seed):
+    if kind == "sk":
+        return instances.ising_to_qubo(instances.sk_bimodal(N, seed))[0]
+    if kind == "gauss":
+        return instances.ising_to_qubo(instances.sk_gaussian(N, seed, scale=2**16))[0]
+    if kind == "random":
+        return instances.random_qubo(N, seed, lo=-300, hi=300)
+    if kind == "random_big":
+        return instances.random_qubo(N, seed, lo=-40000, hi=40000)
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("kind,N,dtype", [
+    ("sk", 1, 0), ("sk", 5, 0), ("sk", 64, 0), ("sk", 100, 0), ("sk", 1000, 0),
+    ("random", 77, 0), ("random", 300, 2), ("random_big", 130, 0), ("gauss", 513, 4),
+    ("sk", 200, 4), ("sk", 129, 2),
+])
+def test_energy(api, kind, N, dtype):
+    Q = _q(kind, N, 3)
+    ctx = api.da_create(Q, dtype)
+    g = np.random.Generator(np.random.PCG64(N))
+    X = g.integers(0, 2, size=(37, N)).astype(np.uint8)
+    E = api.da_energy(ctx, X)
+    want = [oracle.energy(Q, X[r]) for r in range(37)]
+    assert E.tolist() == want
+
+
+@pytest.mark.parametrize("kind,N,dtype,F,rpw", [
+    ("sk", 20, 0, 8, 1), ("sk", 64, 0, 8, 1), ("sk", 64, 2, 4, 2), ("sk", 100, 4, 16, 3),
+    ("random", 70, 0, 8, 2), ("random", 257, 2, 8, 1), ("gauss", 300, 0, 4, 1),
+    ("sk", 513, 0, 8, 1), ("sk", 1000, 2, 8, 2), ("gauss", 1024, 4, 16, 1),
+    ("random_big", 600, 4, 4, 1), ("sk", 1536, 1, 8, 1),
+])
+def test_trace_parity(api, kind, N, dtype, F, rpw):
+    Q = _q(kind, N, 5)
+    if kind == "gauss":
+        T_hi, T_lo, inc = 3.0 * 2**16, 0.05 * 2**16, 2**16
+    elif kind.startswith("random"):
+        T_hi, T_lo, inc = 4000.0, 10.0, 50
+    else:
+        T_hi, T_lo, inc = 3.0 * max(1.0, N ** 0.5), 0.1, 1
+    R, S, L = 5, 700, 16
+    ctx = api.da_create(Q, dtype)
+    sch = api.schedule(T_hi, T_lo, "geometric", L, eoff_inc=inc)
+    gpu = api.da_anneal_ex(ctx, sch, 3, R, S, 11, api.launch(F, rpw, 0), trace=True)
+    ref = oracle.anneal(Q, T_hi=T_hi, T_lo=T_lo, n_levels=L, eoff_inc=inc, replica_base=3,
+                        replicas=R, steps=S, seed=11, trace=True)
+    _same(gpu, ref, ("trace_k", "trace_E", "trace_eoff") + KEYS)
+
+
+@pytest.mark.parametrize("w_lds", [1, -1])
+def test_sk_bimodal_64_full(api, w_lds):
+    """16 replicas x 10^4 steps of an N = 64 +-1 SK instance, escape offset on."""
+    Q = _q("sk", 64, 1)
+    ctx = api.da_create(Q)
+    sch = api.schedule(3.0, 0.05, "geometric", 128, eoff_inc=1)
+    gpu = api.da_anneal_ex(ctx, sch, 0, 16, 10_000, 1, api.launch(0, 0, w_lds))
+    ref = oracle.anneal(Q, T_hi=3.0, T_lo=0.05, n_levels=128, eoff_inc=1, replicas=16,
+                        steps=10_000, seed=1)
+    _same(gpu, ref)
+
+
+@pytest.mark.parametrize("kind,N", [("sk", 1000), ("random", 130), ("gauss", 1024)])
+def test_random_start(api, kind, N):
+    Q = _q(kind, N, 9)
+    ctx = api.da_create(Q)
+    T = 2.0 * 2**16 if kind == "gauss" else 50.0
+    sch = api.schedule(T, T / 20, "linear_beta", 8, eoff_inc=3, init="random")
+    R = 37
+    gpu = api.da_anneal_ex(ctx, sch, 0, R, 0, 7)
+    X0 = np.array([[oracle.init_bit(7, r, i) for i in range(N)] for r in range(R)], np.uint8)
+    assert np.array_equal(gpu["final_x"], X0)
+    assert gpu["final_E"].tolist() == [oracle.energy(Q, X0[r]) for r in range(R)]
+    gpu = api.da_anneal_ex(ctx, sch, 0, R, 300, 7)
+    ref = oracle.anneal(Q, T_hi=T, T_lo=T / 20, kind=1, n_levels=8, eoff_inc=3, init=1,
+                        replicas=R, steps=300, seed=7)
+    _same(gpu, ref)
+
+
+def test_edge_cases(api):
+    # N = 1, zero steps, zero temperature, a single level, S < L
+    Q1 = np.array([[-3]], np.int32)
+    ctx = api.da_create(Q1)
+    out = api.da_anneal(ctx, api.schedule(1.0, 1.0, n_levels=1), 3, 5, 1)
+    ref = oracle.anneal(Q1, T_hi=1.0, T_lo=1.0, n_levels=1, replicas=3, steps=5, seed=1)
+    _same(out, ref)
+    Q = _q("sk", 40, 2)
+    ctx = api.da_create(Q)
+    out = api.da_anneal(ctx, api.schedule(2.0, 1.0), 4, 0, 1)
+    assert np.all(out["final_x"] == 0) and np.all(out["final_E"] == 0)
+    for sch_args in [dict(T_hi=0.0, T_lo=0.0, n_levels=1), dict(T_hi=9.0, T_lo=0.5, n_levels=500)]:
+        sch = api.schedule(sch_args["T_hi"], sch_args["T_lo"], "geometric", sch_args["n_levels"],
+                           eoff_inc=2, init="random")
+        out = api.da_anneal_ex(ctx, sch, 0, 6, 333, 4, trace=True)
+        ref = oracle.anneal(Q, T_hi=sch_args["T_hi"], T_lo=sch_args["T_lo"],
+                            n_levels=sch_args["n_levels"], eoff_inc=2, init=1, replicas=6,
+                            steps=333, seed=4, trace=True)
+        _same(out, ref, ("trace_k", "trace_E", "trace_eoff") + KEYS)
+
+
+def test_offset_ceiling(api):
+    Qb = np.diag([2**30, 2**30, 2**30]).astype(np.int32)
+    ctx = api.da_create(Qb)
+    sch = api.schedule(0.0, 0.0, n_levels=1, eoff_inc=2**29 + 7)
+    out = api.da_anneal_ex(ctx, sch, 0, 2, 4, 1, trace=True)
+    assert out["trace_eoff"].tolist() == [[2**29 + 7, 2**30, 2**30, 2**30]] * 2
+    assert np.all(out["trace_k"] == -1)
+
+
+def test_replica_base_replay(api):
+    Q = _q("sk", 300, 4)
+    ctx = api.da_create(Q)
+    sch = api.schedule(20.0, 0.5, eoff_inc=1)
+    batch = api.da_anneal_ex(ctx, sch, 0, 24, 2000, 3, api.launch(8, 4, 0))
+    for r in (0, 13, 23):
+        one = api.da_anneal_ex(ctx, sch, r, 1, 2000, 3, api.launch(16, 1, 0))
+        for k in KEYS:
+            assert np.array_equal(one[k][0], batch[k][r])
