@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Benchmark of the Digital Annealer parallel-trial step on one MI355X.
+
+One "step" of this benchmark is one whole anneal of the workload: every
+replica runs all its Monte Carlo steps (Algorithm 2 of arXiv:1806.08815) in
+the HIP step kernel, starting from the common zero state.  Inputs (coupling
+matrix, tables, state buffers) are resident in HBM before timing starts; the
+timed region covers K anneals bracketed by device synchronisation.
+
+Prints ONE JSON line:
+  value        flip evaluations per second = replicas * MC steps * N * K / time
+  roofline     row-stream bytes of the step kernel (accepted steps * N *
+               bytes per coupling) / its event-timed duration, against HBM peak
+  cpu_baseline the CPU oracle on one full-length replica of the same workload
+  tts99        time to solution at 99% (Sec. IV), measured the paper's way for
+               the DA: the wall time of one launch with ceil(R99) replicas
+  plain        the same replicas run one launch per replica, beside the
+               single batched launch
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "parallel-trial flip evaluations/s; TTS99 at 1 GPU; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_info():
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def describe(w):
+    return (f"{w.name}: {w.kind} N={w.N}, {w.replicas} replicas x {w.steps} MC steps, "
+            f"{w.schedule} T {w.T_hi:g}->{w.T_lo:g} ({w.n_levels} levels), "
+            f"E_off increment {w.eoff_inc}, {w.init} start, Philox seed {w.seed}")
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="torus2d-bimodal-1024")
+    ap.add_argument("--dtype", type=int, default=None, help="force coupling storage bytes")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(replicas shard across GPUs with no per-step communication, see DESIGN.md)",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1806_08815_amd import api, tts, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = workloads.WORKLOADS[args.workload]
+    Q, const = w.instance()
+    N, R, S = w.N, w.replicas, w.steps
+    dtype_hint = args.dtype if args.dtype is not None else w.dtype_hint
+    ctx = api.da_create(Q, dtype_hint)
+    info = ctx.info()
+    sch = api.schedule(w.T_hi, w.T_lo, w.schedule, w.n_levels, w.eoff_inc, w.init)
+    stream = torch.cuda.current_stream()
+    out = api.device_outputs(R, N)
+
+    def anneal():
+        api.da_anneal_async(ctx, sch, 0, R, S, w.seed, None, out, stream)
+
+    print(f"[bench] {describe(w)}; storage int{8 * info['dtype']} x{info['wscale']}",
+          file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        anneal()
+    torch.cuda.synchronize()
+    api.da_reset_kernel_stats(ctx)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        anneal()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ks = api.da_last_kernel_stats(ctx)
+    kernel_s = ks["total_ms"] / 1e3 / ks["launches"]
+    n_acc = out["n_accept"].cpu().numpy()
+    best_E = out["best_E"].cpu().numpy()
+    best_x0 = out["best_x"][0].cpu().numpy()
+    final_x0 = out["final_x"][0].cpu().numpy()
+    flip_evals = float(R) * S * N * args.steps
+    value = flip_evals / elapsed
+    row_bytes = float(n_acc.sum()) * N * info["dtype"]
+    achieved = row_bytes / kernel_s / 1e9
+    print(f"[bench] {args.steps} anneals in {elapsed:.3f} s; step kernel {kernel_s * 1e3:.3f} ms "
+          f"per launch; {value:.4g} flip-evals/s; {achieved:.1f} GB/s row stream",
+          file=sys.stderr, flush=True)
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "flip-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": describe(w),
+            "N": N, "replicas": R, "mc_steps": S,
+            "coupling_storage": f"int{8 * info['dtype']}",
+            "wscale": info["wscale"],
+            "launch": {k: ks[k] for k in ("blocks", "threads", "flips_per_lane",
+                                          "replicas_per_block", "w_in_lds")},
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": "k_run (step kernel)",
+            "kernel_ms": kernel_s * 1e3,
+            "bytes_per_launch": row_bytes,
+            "accepted_step_fraction": float(n_acc.sum()) / (R * S),
+            "ns_per_mc_step": kernel_s / S * 1e9,
+        },
+    }
+
+    if not args.skip_cpu:
+        import oracle
+        model, ncpu = cpu_info()
+        t0 = time.perf_counter()
+        ref = oracle.anneal(Q, T_hi=w.T_hi, T_lo=w.T_lo,
+                            kind=0 if w.schedule == "geometric" else 1,
+                            n_levels=w.n_levels, eoff_inc=w.eoff_inc,
+                            init=0 if w.init == "zeros" else 1, replicas=1, replica_base=0,
+                            steps=S, seed=w.seed)
+        t_cpu = time.perf_counter() - t0
+        same = (int(ref["best_E"][0]) == int(best_E[0]) and int(ref["n_accept"][0]) == int(n_acc[0])
+                and np.array_equal(ref["best_x"][0], best_x0)
+                and np.array_equal(ref["final_x"][0], final_x0))
+        result["cpu_baseline"] = {
+            "value": S * N / t_cpu,
+            "unit": "flip-evals/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"replica 0 of {R}, all {S} MC steps of the same schedule, "
+                      f"{t_cpu:.1f} s single-threaded on {model} ({ncpu} host CPUs)",
+            "matches_gpu_replica0": bool(same),
+        }
+        print(f"[bench] oracle: {t_cpu:.1f} s, parity with GPU replica 0: {same}",
+              file=sys.stderr, flush=True)
+
+    if not args.skip_extras:
+        # one launch per replica, on the same stream, same outputs per replica
+        one = api.device_outputs(1, N)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in range(R):
+            api.da_anneal_async(ctx, sch, r, 1, S, w.seed, None, one, stream)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        same_last = int(one["best_E"][0].item()) == int(best_E[R - 1])
+        result["plain"] = {
+            "form": f"{R} launches of 1 replica each",
+            "seconds": t_plain,
+            "flip_evals_per_s": float(R) * S * N / t_plain,
+            "batched_speedup": t_plain / (elapsed / args.steps),
+            "same_result_as_batched": bool(same_last),
+        }
+        print(f"[bench] plain per-replica launches: {t_plain:.2f} s", file=sys.stderr, flush=True)
+
+        E_ref = int(best_E.min())
+        y = tts.success_count(best_E, E_ref)
+
+        def time_launch(reps):
+            o = api.device_outputs(reps, N)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            api.da_anneal_async(ctx, sch, 0, reps, S, w.seed, None, o, stream)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t
+
+        t99 = tts.tts99_measured(y, R, time_launch)
+        result["tts99"] = {
+            "E_ref": E_ref + int(const),
+            "E_ref_kind": f"best over {R} replicas (upper bound on the optimum)",
+            "successes": y, "runs": R, "theta_median": t99["theta"], "r99": t99["r99"],
+            "replicas_launched": t99["replicas"], "seconds": t99["tts_s"],
+        }
+
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

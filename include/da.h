@@ -114,25 +114,32 @@ typedef struct da_trace {
  * table).  Results never depend on them.
  *   flips_per_lane      4, 8 or 16 variables per GPU lane
  *   replicas_per_block  replicas sharing one workgroup (1..16)
- *   w_in_lds            1: stage W in LDS when it fits; -1: never; 0: auto */
+ *   w_in_lds            1: stage W in LDS when it fits; -1: never; 0: auto
+ *   rng_ahead           1: generate each step's random numbers one step
+ *                       ahead, under the row fetch; -1: lazily, only for
+ *                       undecided flips; 0: auto */
 typedef struct da_launch {
     int32_t flips_per_lane;
     int32_t replicas_per_block;
     int32_t w_in_lds;
-    int32_t reserved;
+    int32_t rng_ahead;
 } da_launch;
 
-/* What the last kernel launch of a context looked like and how long it took
- * (HIP events on the launch stream around the main step kernel). */
+/* What the step-kernel launches of a context looked like and how long they
+ * took: HIP events recorded on the launch stream right around every step
+ * kernel launch (one anneal = one launch; a PT call = all its rounds). */
 typedef struct da_kernel_stats {
-    double kernel_ms;          /* event-timed duration of the step kernel(s) */
-    int64_t launches;          /* step-kernel launches it covers             */
+    double kernel_ms;          /* duration of the last anneal / PT call's kernels */
+    double total_ms;           /* summed over calls since da_reset_kernel_stats   */
+    int64_t launches;          /* calls summed in total_ms                        */
     int32_t blocks;            /* grid size of the step kernel               */
     int32_t threads;           /* workgroup size                             */
     int32_t flips_per_lane;
     int32_t replicas_per_block;
     int32_t w_in_lds;
+    int32_t rng_ahead;
     int32_t dtype;             /* bytes per stored coupling                  */
+    int32_t reserved;
 } da_kernel_stats;
 
 /* Static facts about a context. */
@@ -234,9 +241,12 @@ int da_pt(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t r
  * DA_EDEVICE. */
 int da_energy(da_ctx *ctx, const uint8_t *x, int32_t count, int64_t *E);
 
-/* Stats of the context's last anneal / PT call (synchronises with its end
- * event). */
+/* Stats of the context's step kernels (synchronises with the last end event;
+ * call it outside timed regions). */
 int da_last_kernel_stats(da_ctx *ctx, da_kernel_stats *stats);
+
+/* Starts a new accumulation window for total_ms / launches. */
+int da_reset_kernel_stats(da_ctx *ctx);
 
 /* Last error message of ctx, or of the calling thread when ctx is NULL. */
 const char *da_last_error(const da_ctx *ctx);

@@ -47,13 +47,14 @@ class da_trace(ctypes.Structure):
 
 class da_launch(ctypes.Structure):
     _fields_ = [("flips_per_lane", _i32), ("replicas_per_block", _i32), ("w_in_lds", _i32),
-                ("reserved", _i32)]
+                ("rng_ahead", _i32)]
 
 
 class da_kernel_stats(ctypes.Structure):
-    _fields_ = [("kernel_ms", _dbl), ("launches", _i64), ("blocks", _i32), ("threads", _i32),
+    _fields_ = [("kernel_ms", _dbl), ("total_ms", _dbl), ("launches", _i64), ("blocks", _i32),
+                ("threads", _i32),
                 ("flips_per_lane", _i32), ("replicas_per_block", _i32), ("w_in_lds", _i32),
-                ("dtype", _i32)]
+                ("rng_ahead", _i32), ("dtype", _i32), ("reserved", _i32)]
 
 
 class da_info(ctypes.Structure):
@@ -117,6 +118,7 @@ def lib() -> ctypes.CDLL:
                          ctypes.POINTER(da_pt_result)]),
         "da_energy": (_i32, [_P, _P, _i32, _P]),
         "da_last_kernel_stats": (_i32, [_P, ctypes.POINTER(da_kernel_stats)]),
+        "da_reset_kernel_stats": (_i32, [_P]),
         "da_last_error": (ctypes.c_char_p, [_P]),
         "da_strerror": (ctypes.c_char_p, [_i32]),
         "da_threshold_table": (_i32, [_dbl, _P]),
@@ -156,8 +158,9 @@ def schedule(T_hi: float, T_lo: float, kind: str | int = "geometric", n_levels: 
     return da_schedule(float(T_hi), float(T_lo), int(k), int(n_levels), int(eoff_inc), int(i))
 
 
-def launch(flips_per_lane: int = 0, replicas_per_block: int = 0, w_in_lds: int = 0) -> da_launch:
-    return da_launch(int(flips_per_lane), int(replicas_per_block), int(w_in_lds), 0)
+def launch(flips_per_lane: int = 0, replicas_per_block: int = 0, w_in_lds: int = 0,
+           rng_ahead: int = 0) -> da_launch:
+    return da_launch(int(flips_per_lane), int(replicas_per_block), int(w_in_lds), int(rng_ahead))
 
 
 class Ctx:
@@ -313,6 +316,10 @@ def da_last_kernel_stats(ctx: Ctx) -> dict:
     st = da_kernel_stats()
     _check(lib().da_last_kernel_stats(ctx.ptr, ctypes.byref(st)), ctx.ptr)
     return {f: getattr(st, f) for f, _ in da_kernel_stats._fields_}
+
+
+def da_reset_kernel_stats(ctx: Ctx) -> None:
+    _check(lib().da_reset_kernel_stats(ctx.ptr), ctx.ptr)
 
 
 def da_threshold_table(T: float) -> np.ndarray:

@@ -18,6 +18,7 @@ namespace dapt {
 
 namespace {
 thread_local std::string t_err;
+constexpr size_t kEventPool = 1024;
 }  // namespace
 
 void set_thread_error(const std::string &msg) { t_err = msg; }
@@ -99,8 +100,14 @@ int validate_schedule(const da_schedule *s, std::string &err) {
 // Launch shape: F variables per lane, NW = ceil(N / 64F) waves per replica,
 // RPW replicas per workgroup.  W goes to LDS when small (it then serves every
 // row fetch at LDS latency).
-LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch) {
+LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch,
+                         bool anneal_mode) {
     LaunchShape sh;
+    const int stage = anneal_mode ? 1 : 0;
+    const int ahead = launch ? launch->rng_ahead : 0;
+    // Ahead-of-time draws pay off while the CUs have spare issue slots (few
+    // replicas per CU); lazy draws save ALU work when the chip is full.
+    sh.pre = ahead > 0 ? 1 : (ahead < 0 ? 0 : (R <= 512 ? 1 : 0));
     sh.F = (launch && launch->flips_per_lane) ? launch->flips_per_lane : 8;
     if (sh.F != 4 && sh.F != 8 && sh.F != 16) sh.F = 8;
     sh.NW = (ctx->N + 64 * sh.F - 1) / (64 * sh.F);
@@ -117,10 +124,10 @@ LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch) 
     sh.w_lds = (want >= 0 && w_bytes <= (want > 0 ? 128 * 1024 : 64 * 1024)) ? 1 : 0;
     sh.threads = 64 * sh.NW * sh.RPW;
     sh.blocks = (R + sh.RPW - 1) / sh.RPW;
-    sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, sh.w_lds ? (int)w_bytes : 0);
+    sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, sh.w_lds ? (int)w_bytes : 0, stage);
     if (sh.lds > 160 * 1024 && sh.w_lds) {
         sh.w_lds = 0;
-        sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0);
+        sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0, stage);
     }
     return sh;
 }
@@ -171,6 +178,35 @@ int init_state(da_ctx *ctx, const JobDesc &J, int init, hipStream_t stream) {
         if (!e) e = launch_energy_from_fields(J, J.x, J.h, J.R, J.E, true, stream);
     }
     return check_hip(ctx, (hipError_t)e, "state initialisation launch");
+}
+
+int next_events(da_ctx *ctx, hipEvent_t &e0, hipEvent_t &e1) {
+    if (ctx->ev_used == kEventPool) {
+        // fold the window into running totals so the pool stays bounded
+        int rc = check_hip(ctx, hipEventSynchronize(ctx->ev1), "event synchronise");
+        for (size_t q = 0; q < ctx->ev_used && !rc; ++q) {
+            float ms = 0.f;
+            rc = check_hip(ctx, hipEventElapsedTime(&ms, ctx->ev_pool[q].first, ctx->ev_pool[q].second),
+                           "event elapsed time");
+            ctx->folded_ms += ms;
+        }
+        if (rc) return rc;
+        ctx->folded_calls += (int64_t)ctx->ev_used;
+        ctx->ev_used = 0;
+    }
+    if (ctx->ev_used == ctx->ev_pool.size()) {
+        hipEvent_t a = nullptr, b = nullptr;
+        int rc = check_hip(ctx, hipEventCreate(&a), "event create");
+        if (!rc) rc = check_hip(ctx, hipEventCreate(&b), "event create");
+        if (rc) return rc;
+        ctx->ev_pool.emplace_back(a, b);
+    }
+    e0 = ctx->ev_pool[ctx->ev_used].first;
+    e1 = ctx->ev_pool[ctx->ev_used].second;
+    ++ctx->ev_used;
+    ctx->ev0 = e0;
+    ctx->ev1 = e1;
+    return DA_OK;
 }
 
 }  // namespace dapt
@@ -244,13 +280,14 @@ int copy_outputs_to_host(da_ctx *ctx, const JobDesc &J, int32_t R, const da_resu
 }
 
 void record_stats(da_ctx *ctx, const LaunchShape &sh, int64_t launches) {
+    (void)launches;
     ctx->last = da_kernel_stats{};
-    ctx->last.launches = launches;
     ctx->last.blocks = sh.blocks;
     ctx->last.threads = sh.threads;
     ctx->last.flips_per_lane = sh.F;
     ctx->last.replicas_per_block = sh.RPW;
     ctx->last.w_in_lds = sh.w_lds;
+    ctx->last.rng_ahead = sh.pre;
     ctx->last.dtype = ctx->dtype;
     ctx->have_stats = true;
 }
@@ -271,11 +308,14 @@ int enqueue_anneal(da_ctx *ctx, const da_schedule *schedule, int64_t replica_bas
     if (!lt) return fail(ctx, DA_ENOMEM, err);
     ctx->keep_tables = lt;
     if (!ctx->st.ensure(replicas, ctx->ld, err)) return fail(ctx, DA_ENOMEM, err);
-    const LaunchShape sh = choose_shape(ctx, replicas, launch);
+    const LaunchShape sh = choose_shape(ctx, replicas, launch, true);
     J = make_job(ctx, *lt, replicas, (uint32_t)replica_base, seed, steps, *schedule, sh);
     rc = init_state(ctx, J, schedule->init, s);
     if (rc) return rc;
-    rc = check_hip(ctx, hipEventRecord(ctx->ev0, s), "event record");
+    hipEvent_t e0, e1;
+    rc = next_events(ctx, e0, e1);
+    if (rc) return rc;
+    rc = check_hip(ctx, hipEventRecord(e0, s), "event record");
     if (rc) return rc;
     if (steps > 0) {
         TraceDesc T{nullptr, nullptr, nullptr, steps};
@@ -284,13 +324,14 @@ int enqueue_anneal(da_ctx *ctx, const da_schedule *schedule, int64_t replica_bas
             T.E = trace_dev->E;
             T.eoff = trace_dev->eoff;
         }
-        const int e = launch_run(J, sh.F, trace_dev ? &T : nullptr, sh.blocks, sh.threads, sh.lds, s);
+        const int e = launch_run(J, sh.F, sh.pre != 0, trace_dev ? &T : nullptr, sh.blocks,
+                                 sh.threads, sh.lds, s);
         rc = check_hip(ctx, (hipError_t)e, "step kernel launch");
         if (rc) return rc;
     }
-    rc = check_hip(ctx, hipEventRecord(ctx->ev1, s), "event record");
+    rc = check_hip(ctx, hipEventRecord(e1, s), "event record");
     if (rc) return rc;
-    record_stats(ctx, sh, steps > 0 ? 1 : 0);
+    record_stats(ctx, sh, 1);
     return DA_OK;
 }
 
@@ -360,8 +401,6 @@ int da_create(const int32_t *Q, int32_t N, int32_t dtype_hint, da_ctx **out) {
     if (!rc) rc = check_hip(nullptr, hipMemcpy(ctx->d_W, Wd.data(), Wd.size(), hipMemcpyHostToDevice), "W upload");
     if (!rc) rc = check_hip(nullptr, hipMemcpy(ctx->d_b, bd.data(), ld * 4, hipMemcpyHostToDevice), "b upload");
     if (!rc) rc = check_hip(nullptr, hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking), "stream");
-    if (!rc) rc = check_hip(nullptr, hipEventCreate(&ctx->ev0), "event");
-    if (!rc) rc = check_hip(nullptr, hipEventCreate(&ctx->ev1), "event");
     if (rc) {
         da_destroy(ctx);
         return rc;
@@ -380,8 +419,10 @@ void da_destroy(da_ctx *ctx) {
     for (void *p : {(void *)ctx->pt_slot2rep, (void *)ctx->pt_lvl, (void *)ctx->pt_swaps,
                     (void *)ctx->pt_round, (void *)ctx->pt_dbeta, (void *)ctx->pt_lnU})
         if (p) (void)hipFree(p);
-    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
-    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    for (auto &pr : ctx->ev_pool) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
     delete ctx;
 }
@@ -478,11 +519,12 @@ int da_anneal_batch(const da_batch_item *items, int32_t count, void *stream) {
         ctx->keep_tables = lt;
         if (!ctx->st.ensure(it.replicas, ctx->ld, err)) return fail(ctx, DA_ENOMEM, err);
         // every workgroup of the persistent launch has 16 waves
-        da_launch shape_req{8, 16, -1, 0};
-        LaunchShape sh = choose_shape(ctx, it.replicas, &shape_req);
+        da_launch shape_req{8, 16, -1, -1};
+        LaunchShape sh = choose_shape(ctx, it.replicas, &shape_req, true);
         sh.RPW = 16 / sh.NW;
         sh.w_lds = 0;
-        sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0);
+        sh.pre = 0;
+        sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0, 1);
         if (sh.F != 8) return fail(ctx, DA_EINVAL, "batched launch needs N <= 8192");
         lds = std::max(lds, sh.lds);
         jobs[(size_t)a] = make_job(ctx, *lt, it.replicas, (uint32_t)it.replica_base, it.seed,
@@ -509,7 +551,9 @@ int da_anneal_batch(const da_batch_item *items, int32_t count, void *stream) {
     if (!rc) rc = check_hip(c0, hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * sizeof(JobDesc), hipMemcpyHostToDevice, s), "batch upload");
     if (!rc && !work.empty()) rc = check_hip(c0, hipMemcpyAsync(d_items, work.data(), work.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s), "batch upload");
     if (!rc) rc = check_hip(c0, (hipError_t)launch_fill_i32(d_counter, 0, 1, s), "counter reset");
-    if (!rc) rc = check_hip(c0, hipEventRecord(c0->ev0, s), "event record");
+    hipEvent_t be0 = nullptr, be1 = nullptr;
+    if (!rc) rc = next_events(c0, be0, be1);
+    if (!rc) rc = check_hip(c0, hipEventRecord(be0, s), "event record");
     if (!rc && !work.empty()) {
         int dev = 0, cus = 256;
         (void)hipGetDevice(&dev);
@@ -522,7 +566,7 @@ int da_anneal_batch(const da_batch_item *items, int32_t count, void *stream) {
         c0->last.blocks = blocks;
         c0->last.threads = 1024;
     }
-    if (!rc) rc = check_hip(c0, hipEventRecord(c0->ev1, s), "event record");
+    if (!rc) rc = check_hip(c0, hipEventRecord(be1, s), "event record");
     for (int32_t a = 0; a < count && !rc; ++a)
         rc = extract_outputs(items[a].ctx, jobs[(size_t)a], items[a].replicas, &items[a].out_dev, s);
     // the device tables of the batch must outlive the kernel
@@ -586,7 +630,7 @@ int da_pt(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t r
     if (rc) return rc;
 
     da_schedule sched{temps[0], temps[0], DA_SCHED_GEOMETRIC, 1, eoff_inc, DA_INIT_RANDOM};
-    const LaunchShape sh = choose_shape(ctx, R, nullptr);
+    const LaunchShape sh = choose_shape(ctx, R, nullptr, false);
     JobDesc J = make_job(ctx, *lt, R, 0u, seed, 0, sched, sh);
     J.L = M;
     J.lvl_of_rep = ctx->pt_lvl;
@@ -594,12 +638,15 @@ int da_pt(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t r
     J.K = steps_per_round;
     rc = init_state(ctx, J, DA_INIT_RANDOM, s);
     if (!rc) rc = check_hip(ctx, (hipError_t)launch_pt_setup(ctx->pt_slot2rep, ctx->pt_lvl, ctx->pt_swaps, ctx->pt_round, M, chains, s), "PT setup");
-    if (!rc) rc = check_hip(ctx, hipEventRecord(ctx->ev0, s), "event record");
+    hipEvent_t pe0 = nullptr, pe1 = nullptr;
+    if (!rc) rc = next_events(ctx, pe0, pe1);
+    if (!rc) rc = check_hip(ctx, hipEventRecord(pe0, s), "event record");
     if (rc) return rc;
 
     auto one_round = [&]() -> int {
         int e = 0;
-        if (steps_per_round > 0) e = launch_run(J, sh.F, nullptr, sh.blocks, sh.threads, sh.lds, s);
+        if (steps_per_round > 0)
+            e = launch_run(J, sh.F, sh.pre != 0, nullptr, sh.blocks, sh.threads, sh.lds, s);
         if (!e)
             e = launch_pt_exchange(J.E, ctx->pt_slot2rep, ctx->pt_lvl, ctx->pt_dbeta, ctx->pt_lnU, M,
                                    chains, seed, ctx->pt_round, ctx->pt_swaps, s);
@@ -624,9 +671,9 @@ int da_pt(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t r
         if (rc) return rc;
     }
     for (; done < rounds && !rc; ++done) rc = check_hip(ctx, (hipError_t)one_round(), "PT round launch");
-    if (!rc) rc = check_hip(ctx, hipEventRecord(ctx->ev1, s), "event record");
+    if (!rc) rc = check_hip(ctx, hipEventRecord(pe1, s), "event record");
     if (rc) return rc;
-    record_stats(ctx, sh, rounds);
+    record_stats(ctx, sh, 1);
 
     if (out) {
         da_result o{out->best_x, out->best_E, out->final_x, out->final_E, out->n_accept};
@@ -675,14 +722,33 @@ int da_energy(da_ctx *ctx, const uint8_t *x, int32_t count, int64_t *E) {
 
 int da_last_kernel_stats(da_ctx *ctx, da_kernel_stats *stats) {
     if (!ctx || !stats) return fail(ctx, DA_EINVAL, "null argument");
-    if (!ctx->have_stats) return fail(ctx, DA_EINVAL, "no launch recorded yet");
+    if (!ctx->have_stats || ctx->ev_used == 0) return fail(ctx, DA_EINVAL, "no launch recorded yet");
     int rc = check_hip(ctx, hipEventSynchronize(ctx->ev1), "event synchronise");
     if (rc) return rc;
+    double total = 0.0;
     float ms = 0.f;
-    rc = check_hip(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1), "event elapsed time");
-    if (rc) return rc;
+    for (size_t q = 0; q < ctx->ev_used; ++q) {
+        rc = check_hip(ctx, hipEventElapsedTime(&ms, ctx->ev_pool[q].first, ctx->ev_pool[q].second),
+                       "event elapsed time");
+        if (rc) return rc;
+        total += ms;
+    }
     ctx->last.kernel_ms = ms;
+    ctx->last.total_ms = total + ctx->folded_ms;
+    ctx->last.launches = (int64_t)ctx->ev_used + ctx->folded_calls;
     *stats = ctx->last;
+    return DA_OK;
+}
+
+int da_reset_kernel_stats(da_ctx *ctx) {
+    if (!ctx) return fail(nullptr, DA_EINVAL, "ctx is null");
+    if (ctx->ev1) {
+        const int rc = check_hip(ctx, hipEventSynchronize(ctx->ev1), "event synchronise");
+        if (rc) return rc;
+    }
+    ctx->ev_used = 0;
+    ctx->folded_ms = 0.0;
+    ctx->folded_calls = 0;
     return DA_OK;
 }
 

@@ -87,7 +87,7 @@ int launch_rand_bits(uint8_t *X, int32_t R, int32_t N, int32_t ld, uint32_t rid_
 int launch_fields(const JobDesc &J, const uint8_t *X, int32_t R, int32_t *H, void *stream);
 int launch_energy_from_fields(const JobDesc &J, const uint8_t *X, const int32_t *H, int32_t R,
                               int64_t *E_out, bool finish_state, void *stream);
-int launch_run(const JobDesc &J, int F, const TraceDesc *trace, int blocks, int threads,
+int launch_run(const JobDesc &J, int F, bool pre, const TraceDesc *trace, int blocks, int threads,
                size_t lds_bytes, void *stream);
 int launch_batch(const JobDesc *jobs_dev, const BatchItem *items_dev, int n_items,
                  int32_t *counter_dev, int blocks, int threads, size_t lds_bytes, void *stream);
@@ -101,7 +101,8 @@ int launch_extract(const JobDesc &J, const uint8_t *src_x, uint8_t *dst_x, int32
 int launch_copy_i64(const int64_t *src, int64_t *dst, int32_t n, void *stream);
 int launch_fill_i32(int32_t *dst, int32_t value, int64_t n, void *stream);
 
-// Workgroup LDS bytes the run kernel needs for a launch shape.
-size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes);
+// Workgroup LDS bytes the run kernel needs for a launch shape (stage_brk: the
+// level's bracket table is staged in LDS, anneal mode).
+size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk);
 
 }  // namespace dapt

@@ -49,14 +49,12 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
             k0 += kPhiloxW0;
             k1 += kPhiloxW1;
         }
-        const uint32_t hi0 = __umulhi(kPhiloxM0, c0);
-        const uint32_t lo0 = kPhiloxM0 * c0;
-        const uint32_t hi1 = __umulhi(kPhiloxM1, c2);
-        const uint32_t lo1 = kPhiloxM1 * c2;
-        c0 = hi1 ^ c1 ^ k0;
-        c1 = lo1;
-        c2 = hi0 ^ c3 ^ k1;
-        c3 = lo0;
+        const uint64_t p0 = (uint64_t)kPhiloxM0 * (uint64_t)c0;   // v_mad_u64_u32
+        const uint64_t p1 = (uint64_t)kPhiloxM1 * (uint64_t)c2;
+        c0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        c1 = (uint32_t)p1;
+        c2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c3 = (uint32_t)p0;
     }
     return make_uint4(c0, c1, c2, c3);
 }
@@ -127,21 +125,51 @@ __device__ __forceinline__ int64_t next_level_step(int lvl, int32_t L, int64_t S
     return ((int64_t)(lvl + 1) * S + L - 1) / L;
 }
 
+// DPP inclusive prefix sum within each row of 16 lanes.
+__device__ __forceinline__ int row16_incl_scan(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    return v;
+}
+
 }  // namespace
 
-size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes) {
+size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk) {
+    (void)F;
     size_t per_slot = 0;
-    if (NW > 1) per_slot = 2 * (size_t)NW * 4 + 2 * (size_t)NW * 64 * 4 + 2 * (size_t)NW * 64 * F * 4;
+    if (NW > 1) per_slot = 2 * (size_t)NW * 4 + 2 * (size_t)NW * 64 * 4 + 2 * 4;
     size_t w = (size_t)((w_lds_bytes + 15) & ~15);
-    return w + per_slot * RPW;
+    size_t b = stage_brk ? (size_t)kMaxBuckets * 4 : 0;
+    return w + b + ((per_slot * RPW + 15) & ~(size_t)15);
 }
 
 // Runs steps [s0, s1) for the replicas of one workgroup.  `blk` selects which
 // replicas of the job (rows blk*RPW ..).  All waves of the workgroup execute
 // the same number of loop iterations and barriers.
-template <typename WT, int F, bool TRACE>
+//
+// PRE: the random numbers of step s+1 (they depend only on seed, replica,
+// step and variable) are generated right after the row fetch of step s is
+// issued, so Philox runs in the shadow of the memory latency instead of on the
+// step's critical path.  Without PRE they are generated lazily, only for
+// lanes with in-band flips (less ALU work when most flips are decided by the
+// band, e.g. at low temperature).
+// STAGE: one level per workgroup (anneal), its brackets live in LDS; else
+// (parallel tempering) every replica has its own level, read through L1/L2.
+//
+// Multi-wave replicas (NW > 1) exchange, once per step, each lane's accepted
+// mask and x bits plus each wave's accepted count through LDS, double-buffered
+// by step parity, around one workgroup barrier.  The energy change of the
+// chosen flip is handed to the other waves one step later through the same
+// buffers (the owning lane writes it after the selection), so it never adds
+// an LDS round trip to the critical path; the energy and the best-state check
+// of step s therefore complete after barrier s+1, before step s+1 flips.
+template <typename WT, int F, bool TRACE, bool PRE, bool STAGE>
 __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *smem,
                                           const TraceDesc &T) {
+    constexpr int NB = (F + 7) / 8;   // Philox blocks per lane
+    typedef typename VecOf<WT, F>::type RowV;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int NW = J.NW;
@@ -152,11 +180,13 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     const int rr = blk * J.RPW + slot;
     const bool active = (slot < J.RPW) && (rr < J.R);
     const bool lane_has = active && (i0 < J.ld);
+    const int col0 = lane_has ? i0 : 0;     // row column this lane reads (ghost lanes: 0)
     const uint32_t rid = J.rid_base + (uint32_t)rr;
     const uint32_t k0 = (uint32_t)J.seed;
     const uint32_t k1 = (uint32_t)(J.seed >> 32);
     const int ld = J.ld;
     const int wscale = J.wscale;
+    constexpr bool stage = STAGE;
 
     int64_t s0 = J.s0, s1 = J.s1;
     if (J.round_ptr) {
@@ -165,19 +195,19 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         s1 = s0 + J.K;
     }
 
-    // --- LDS carve-up ----------------------------------------------------
+    // --- LDS carve-up: [W][brackets][selection slots] ------------------------
     const int w_bytes = J.w_lds ? ((J.N * ld * (int)sizeof(WT) + 15) & ~15) : 0;
-    WT *Wl = reinterpret_cast<WT *>(smem);
-    uint8_t *sel = smem + w_bytes;
-    const size_t slot_bytes =
-        (NW > 1) ? (2 * (size_t)NW * 4 + 2 * (size_t)NW * 64 * 4 + 2 * (size_t)NW * 64 * F * 4) : 0;
+    const WT *Wl = reinterpret_cast<const WT *>(smem);
+    uint32_t *brk_l = reinterpret_cast<uint32_t *>(smem + w_bytes);
+    uint8_t *sel = smem + w_bytes + (stage ? kMaxBuckets * 4 : 0);
+    const size_t slot_bytes = (NW > 1) ? (2 * (size_t)NW * 4 + 2 * (size_t)NW * 64 * 4 + 2 * 4) : 0;
     int *tot = reinterpret_cast<int *>(sel + slot_bytes * slot);        // [2][NW]
     uint32_t *rec = reinterpret_cast<uint32_t *>(tot + 2 * NW);        // [2][NW*64]
-    int *dv = reinterpret_cast<int *>(rec + 2 * NW * 64);               // [2][NW*64*F]
+    int *dEs = reinterpret_cast<int *>(rec + 2 * NW * 64);              // [2]
 
     if (J.w_lds) {
         const uint4 *src = reinterpret_cast<const uint4 *>(J.W);
-        uint4 *dst = reinterpret_cast<uint4 *>(Wl);
+        uint4 *dst = reinterpret_cast<uint4 *>(smem);
         const int n16 = (J.N * ld * (int)sizeof(WT)) / 16;
         for (int q = threadIdx.x; q < n16; q += blockDim.x) dst[q] = src[q];
         __syncthreads();
@@ -215,7 +245,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     // --- level in force ----------------------------------------------------
     int lvl;
     int64_t s_next;
-    if (J.lvl_of_rep) {
+    if (!stage) {
         lvl = active ? J.lvl_of_rep[rr] : 0;
         s_next = INT64_MAX;
     } else {
@@ -223,12 +253,31 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         s_next = next_level_step(lvl, J.L, J.S);
     }
     LevelHdr hd = J.hdr[lvl];
+    auto stage_brackets = [&]() {
+        __syncthreads();
+        const int nb = hd.tmax > hd.tmin ? ((hd.tmax - hd.tmin - 1) >> hd.sh) + 1 : 0;
+        for (int q = threadIdx.x; q < nb; q += blockDim.x) brk_l[q] = J.brk[hd.off + q];
+        __syncthreads();
+    };
+    if (stage) stage_brackets();
 
+    uint4 rb[NB];
+    uint32_t vsel = 0;
+    auto gen_draws = [&](int64_t st) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+            rb[q] = philox((uint32_t)(i0 >> 3) + q, (uint32_t)st, rid, kTagMetropolis, k0, k1);
+        vsel = philox(0u, (uint32_t)st, rid, kTagSelect, k0, k1).x;
+    };
+    if (PRE) gen_draws(s0);
+
+    bool pend = false;   // NW > 1: the previous step's energy change is in dEs
     for (int64_t s = s0; s < s1; ++s) {
         if (s == s_next) {
             lvl = level_of(s, J.L, J.S);
             s_next = next_level_step(lvl, J.L, J.S);
             hd = J.hdr[lvl];
+            if (stage) stage_brackets();
         }
         const int par = (int)(s & 1);
 
@@ -244,25 +293,37 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             else if (v && dd <= hd.tmax) inb |= 1u << f;
         }
 
-        // 2. in-band flips: Philox draw and bracket (table only when needed)
+        // 2. in-band flips: 16-bit draw and bracket.  All bracket reads are
+        // issued together (out-of-band flips read entry 0) and waited on once;
+        // the threshold table itself is read only inside a non-exact bracket.
         if (inb) {
-            uint4 rb[(F + 7) / 8];
+            if (!PRE) {
 #pragma unroll
-            for (int q = 0; q < (F + 7) / 8; ++q)
-                rb[q] = philox((uint32_t)(i0 >> 3) + q, (uint32_t)s, rid, kTagMetropolis, k0, k1);
-            const uint32_t *brk = J.brk + hd.off;
-            const int32_t *thr = J.thr + (size_t)lvl * 65536;
+                for (int q = 0; q < NB; ++q)
+                    rb[q] = philox((uint32_t)(i0 >> 3) + q, (uint32_t)s, rid, kTagMetropolis, k0, k1);
+            }
+            uint32_t u[F], e[F];
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                const int slice = (F >= 8) ? (f & 7) : ((i0 & 7) + f);
+                const uint32_t wv = word_of(rb[f >> 3], slice >> 1);
+                u[f] = (slice & 1) ? (wv >> 16) : (wv & 0xFFFFu);
+                const int bi = ((inb >> f) & 1u) ? ((d[f] - hd.tmin - 1) >> hd.sh) : 0;
+                e[f] = stage ? brk_l[bi] : J.brk[hd.off + bi];
+            }
+            uint32_t fine = 0;
 #pragma unroll
             for (int f = 0; f < F; ++f) {
                 if (!((inb >> f) & 1u)) continue;
-                const int slice = (F >= 8) ? (f & 7) : ((i0 & 7) + f);
-                const uint32_t wv = word_of(rb[f >> 3], slice >> 1);
-                const uint32_t u = (slice & 1) ? (wv >> 16) : (wv & 0xFFFFu);
-                const uint32_t e = brk[(d[f] - hd.tmin - 1) >> hd.sh];
-                const uint32_t lo = e & 0xFFFFu, hi = e >> 16;
-                bool a = u < lo;
-                if (!a && u < hi) a = d[f] <= thr[u];
-                if (a) acc |= 1u << f;
+                const uint32_t lo = e[f] & 0xFFFFu, hi = e[f] >> 16;
+                if (u[f] < lo) acc |= 1u << f;
+                else if (u[f] < hi) fine |= 1u << f;
+            }
+            if (fine) {
+                const int32_t *thr = J.thr + (size_t)lvl * 65536;
+#pragma unroll
+                for (int f = 0; f < F; ++f)
+                    if (((fine >> f) & 1u) && d[f] <= thr[u[f]]) acc |= 1u << f;
             }
         }
 
@@ -271,106 +332,132 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         int excl, wtot;
         wave_prefix<CountBits<F>::value>(c, excl, wtot);
 
-        int m, k, xk, dk;
+        int m, k = 0, xk = 0, dk = 0, ts = 0, bit = 0, ws = 0;
         if (NW == 1) {
             m = wtot;
-            if (m == 0) {
-                eoff = min(eoff + J.eoff_inc, kEoffMax);
-                if (TRACE && active && g == 0) {
-                    T.k[rr * T.stride + (s - s0)] = -1;
-                    T.E[rr * T.stride + (s - s0)] = E;
-                    T.eoff[rr * T.stride + (s - s0)] = eoff;
-                }
-                continue;
-            }
-            const uint32_t v = philox(0u, (uint32_t)s, rid, kTagSelect, k0, k1).x;
-            const int j = (int)(((uint64_t)v * (uint32_t)m) >> 32);
-            const int incl = excl + c;
-            const uint64_t bal = ballot(incl > j);
-            const int ts = __ffsll((unsigned long long)bal) - 1;
-            const int rloc = j - readlane(excl, ts);
-            const uint32_t msk = (uint32_t)readlane((int)acc, ts);
-            const int bit = select_bit(msk, rloc);
-            int dsel = d[0];
+            if (m > 0) {
+                const uint32_t v = PRE ? vsel : philox(0u, (uint32_t)s, rid, kTagSelect, k0, k1).x;
+                const int j = (int)(((uint64_t)v * (uint32_t)m) >> 32);
+                const uint64_t bal = ballot(excl + c > j);
+                ts = __ffsll((unsigned long long)bal) - 1;
+                const int rloc = j - readlane(excl, ts);
+                const uint32_t msk = (uint32_t)readlane((int)acc, ts);
+                bit = select_bit(msk, rloc);
+                k = ts * F + bit;
+                xk = (readlane((int)xb, ts) >> bit) & 1;
+                int dsel = d[0];
 #pragma unroll
-            for (int f = 1; f < F; ++f) dsel = (bit == f) ? d[f] : dsel;
-            k = ts * F + bit;
-            xk = (readlane((int)xb, ts) >> bit) & 1;
-            dk = readlane(dsel, ts);
+                for (int f = 1; f < F; ++f) dsel = (bit == f) ? d[f] : dsel;
+                dk = readlane(dsel, ts);
+            }
         } else {
             // publish this wave's lanes, then one barrier
             rec[par * NW * 64 + g] = acc | (xb << 16);
-#pragma unroll
-            for (int f = 0; f < F; ++f) dv[(par * NW * 64 + g) * F + f] = d[f];
             if (lane == 0) tot[par * NW + wr] = wtot;
             __syncthreads();
-            const int tw = (lane < NW) ? tot[par * NW + lane] : 0;
-            int scan = tw;
-#pragma unroll
-            for (int o = 1; o < 16; o <<= 1) {
-                const int t = __shfl_up(scan, o, 64);
-                if (lane >= o) scan += t;
-            }
-            m = readlane(scan, NW - 1);
-            if (m == 0) {
-                eoff = min(eoff + J.eoff_inc, kEoffMax);
-                if (TRACE && active && g == 0) {
-                    T.k[rr * T.stride + (s - s0)] = -1;
-                    T.E[rr * T.stride + (s - s0)] = E;
-                    T.eoff[rr * T.stride + (s - s0)] = eoff;
+            // the previous step's energy change (written by its owner lane)
+            if (pend) {
+                E += (int64_t)dEs[par ^ 1];
+                if (E < bE) {
+                    bE = E;
+                    bxb = xb;
                 }
-                continue;
+                if (TRACE && active && g == 0) T.E[rr * T.stride + (s - 1 - s0)] = E;
+                pend = false;
             }
-            const uint32_t v = philox(0u, (uint32_t)s, rid, kTagSelect, k0, k1).x;
-            const int j = (int)(((uint64_t)v * (uint32_t)m) >> 32);
-            const uint64_t wbal = ballot(lane < NW && scan > j);
-            const int ws = __ffsll((unsigned long long)wbal) - 1;
-            const int jw = j - (readlane(scan, ws) - readlane(tw, ws));
-            const uint32_t r2 = rec[par * NW * 64 + ws * 64 + lane];
-            const int c2 = __popc(r2 & 0xFFFFu);
-            int excl2, tot2;
-            wave_prefix<CountBits<F>::value>(c2, excl2, tot2);
-            const uint64_t bal = ballot(excl2 + c2 > jw);
-            const int ts = __ffsll((unsigned long long)bal) - 1;
-            const int rloc = jw - readlane(excl2, ts);
-            const uint32_t rs = (uint32_t)readlane((int)r2, ts);
-            const int bit = select_bit(rs & 0xFFFFu, rloc);
-            const int gk = ws * 64 + ts;
-            k = gk * F + bit;
-            xk = (rs >> (16 + bit)) & 1;
-            dk = dv[(par * NW * 64 + gk) * F + bit];
+            const int tw = (lane < NW) ? tot[par * NW + lane] : 0;
+            uint32_t r4[4];
+            if (NW <= 4) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) r4[q] = (q < NW) ? rec[par * NW * 64 + q * 64 + lane] : 0u;
+            }
+            const int scan = row16_incl_scan(tw);
+            m = readlane(scan, NW - 1);
+            if (m > 0) {
+                const uint32_t v = PRE ? vsel : philox(0u, (uint32_t)s, rid, kTagSelect, k0, k1).x;
+                const int j = (int)(((uint64_t)v * (uint32_t)m) >> 32);
+                const uint64_t wbal = ballot(lane < NW && scan > j);
+                ws = __ffsll((unsigned long long)wbal) - 1;
+                const int jw = j - (readlane(scan, ws) - readlane(tw, ws));
+                uint32_t r2;
+                if (NW <= 4) {
+                    r2 = r4[0];
+#pragma unroll
+                    for (int q = 1; q < 4; ++q) r2 = (ws == q) ? r4[q] : r2;
+                } else {
+                    r2 = rec[par * NW * 64 + ws * 64 + lane];
+                }
+                const int c2 = __popc(r2 & 0xFFFFu);
+                int excl2, tot2;
+                wave_prefix<CountBits<F>::value>(c2, excl2, tot2);
+                const uint64_t bal = ballot(excl2 + c2 > jw);
+                ts = __ffsll((unsigned long long)bal) - 1;
+                const int rloc = jw - readlane(excl2, ts);
+                const uint32_t rs = (uint32_t)readlane((int)r2, ts);
+                bit = select_bit(rs & 0xFFFFu, rloc);
+                k = (ws * 64 + ts) * F + bit;
+                xk = (rs >> (16 + bit)) & 1;
+            }
         }
 
-        // 4. apply the flip: energy, state, every field from row k of W
-        E += (int64_t)dk + eoff;
-        const int delta = xk ? -1 : 1;
-        if (g == (k / F)) xb ^= 1u << (k % F);
-        if (lane_has) {
-            int w[F];
-            if (J.w_lds) {
+        if (m > 0) {
+            // 4. fetch row k of W (the step's only bulk traffic) ...
+            RowV raw;
+            if (J.w_lds) raw = *reinterpret_cast<const RowV *>(Wl + (size_t)k * ld + col0);
+            else raw = *reinterpret_cast<const RowV *>(reinterpret_cast<const WT *>(J.W) +
+                                                        (size_t)k * ld + col0);
+            // ... and, while it is in flight, the next step's random numbers
+            if (PRE && s + 1 < s1) gen_draws(s + 1);
+            // 5. apply the flip: state, energy, every field from row k
+            const int delta = xk ? -1 : 1;
+            if (g == (k / F)) {
+                if (NW > 1) {
+                    int dsel = d[0];
 #pragma unroll
-                for (int f = 0; f < F; ++f) w[f] = (int)Wl[(size_t)k * ld + i0 + f];
-            } else {
-                load_row<WT, F>(reinterpret_cast<const WT *>(J.W) + (size_t)k * ld + i0, w);
+                    for (int f = 1; f < F; ++f) dsel = (bit == f) ? d[f] : dsel;
+                    dEs[par] = dsel + eoff;
+                }
+                xb ^= 1u << (k % F);
             }
             if (wscale == 1) {
 #pragma unroll
-                for (int f = 0; f < F; ++f) h[f] += delta > 0 ? w[f] : -w[f];
+                for (int f = 0; f < F; ++f) h[f] += delta > 0 ? (int)raw[f] : -(int)raw[f];
             } else {
 #pragma unroll
-                for (int f = 0; f < F; ++f) h[f] += delta * (w[f] * wscale);
+                for (int f = 0; f < F; ++f) h[f] += delta * ((int)raw[f] * wscale);
             }
-        }
-        eoff = 0;
-        ++nacc;
-        if (E < bE) {
-            bE = E;
-            bxb = xb;
+            ++nacc;
+            if (NW == 1) {
+                E += (int64_t)dk + eoff;
+                if (E < bE) {
+                    bE = E;
+                    bxb = xb;
+                }
+            } else {
+                pend = true;
+            }
+            eoff = 0;
+        } else {
+            if (PRE && s + 1 < s1) gen_draws(s + 1);
+            eoff = min(eoff + J.eoff_inc, kEoffMax);
+            k = -1;
         }
         if (TRACE && active && g == 0) {
             T.k[rr * T.stride + (s - s0)] = k;
-            T.E[rr * T.stride + (s - s0)] = E;
             T.eoff[rr * T.stride + (s - s0)] = eoff;
+            if (NW == 1 || k < 0) T.E[rr * T.stride + (s - s0)] = E;
+        }
+    }
+    if (NW > 1) {
+        // the last step's energy change
+        __syncthreads();
+        if (pend) {
+            E += (int64_t)dEs[(int)((s1 - 1) & 1)];
+            if (E < bE) {
+                bE = E;
+                bxb = xb;
+            }
+            if (TRACE && active && g == 0) T.E[rr * T.stride + (s1 - 1 - s0)] = E;
         }
     }
 
@@ -399,10 +486,10 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     }
 }
 
-template <typename WT, int F, bool TRACE>
+template <typename WT, int F, bool TRACE, bool PRE, bool STAGE>
 __global__ __launch_bounds__(1024) void k_run(JobDesc J, TraceDesc T) {
     extern __shared__ __align__(16) uint8_t smem[];
-    run_block<WT, F, TRACE>(J, blockIdx.x, smem, T);
+    run_block<WT, F, TRACE, PRE, STAGE>(J, blockIdx.x, smem, T);
 }
 
 // Persistent batched form: workgroups pull (job, replica-block) items from a
@@ -424,9 +511,9 @@ __global__ __launch_bounds__(1024) void k_batch(const JobDesc *__restrict__ jobs
         const BatchItem bi = items[it];
         JobDesc J = jobs[bi.job];
         const int blk = bi.r0 / J.RPW;
-        if (J.dtype == 1) run_block<int8_t, F, false>(J, blk, smem, T);
-        else if (J.dtype == 2) run_block<int16_t, F, false>(J, blk, smem, T);
-        else run_block<int32_t, F, false>(J, blk, smem, T);
+        if (J.dtype == 1) run_block<int8_t, F, false, false, true>(J, blk, smem, T);
+        else if (J.dtype == 2) run_block<int16_t, F, false, false, true>(J, blk, smem, T);
+        else run_block<int32_t, F, false, false, true>(J, blk, smem, T);
         __syncthreads();
     }
 }
@@ -642,43 +729,56 @@ inline int grid_for(int64_t n, int threads) {
     return (int)g;
 }
 
-template <typename WT, int F, bool TRACE>
+template <typename WT, int F, bool TRACE, bool PRE>
 int launch_run_t(const JobDesc &J, const TraceDesc &T, int blocks, int threads, size_t lds,
                  void *stream) {
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_run<WT, F, TRACE>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_run<WT, F, TRACE, PRE, true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_run<WT, F, TRACE, PRE, false>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_run<WT, F, TRACE>), dim3(blocks), dim3(threads), lds, S(stream), J, T);
+    if (J.lvl_of_rep)
+        hipLaunchKernelGGL((k_run<WT, F, TRACE, PRE, false>), dim3(blocks), dim3(threads), lds,
+                           S(stream), J, T);
+    else
+        hipLaunchKernelGGL((k_run<WT, F, TRACE, PRE, true>), dim3(blocks), dim3(threads), lds,
+                           S(stream), J, T);
     return (int)hipGetLastError();
 }
 
-template <typename WT, bool TRACE>
+template <typename WT, bool TRACE, bool PRE>
 int launch_run_f(const JobDesc &J, int F, const TraceDesc &T, int blocks, int threads, size_t lds,
                  void *stream) {
     switch (F) {
-        case 4: return launch_run_t<WT, 4, TRACE>(J, T, blocks, threads, lds, stream);
-        case 8: return launch_run_t<WT, 8, TRACE>(J, T, blocks, threads, lds, stream);
-        case 16: return launch_run_t<WT, 16, TRACE>(J, T, blocks, threads, lds, stream);
+        case 4: return launch_run_t<WT, 4, TRACE, PRE>(J, T, blocks, threads, lds, stream);
+        case 8: return launch_run_t<WT, 8, TRACE, PRE>(J, T, blocks, threads, lds, stream);
+        case 16: return launch_run_t<WT, 16, TRACE, PRE>(J, T, blocks, threads, lds, stream);
         default: return (int)hipErrorInvalidValue;
     }
 }
+
+template <typename WT>
+int launch_run_w(const JobDesc &J, int F, bool pre, const TraceDesc *trace, int blocks,
+                 int threads, size_t lds, void *stream) {
+    const TraceDesc none{nullptr, nullptr, nullptr, 0};
+    if (trace) {
+        return pre ? launch_run_f<WT, true, true>(J, F, *trace, blocks, threads, lds, stream)
+                   : launch_run_f<WT, true, false>(J, F, *trace, blocks, threads, lds, stream);
+    }
+    return pre ? launch_run_f<WT, false, true>(J, F, none, blocks, threads, lds, stream)
+               : launch_run_f<WT, false, false>(J, F, none, blocks, threads, lds, stream);
+}
 }  // namespace
 
-int launch_run(const JobDesc &J, int F, const TraceDesc *trace, int blocks, int threads,
+int launch_run(const JobDesc &J, int F, bool pre, const TraceDesc *trace, int blocks, int threads,
                size_t lds_bytes, void *stream) {
-    const TraceDesc none{nullptr, nullptr, nullptr, 0};
-    const bool tr = trace != nullptr;
-    const TraceDesc &T = tr ? *trace : none;
     switch (J.dtype) {
-        case 1: return tr ? launch_run_f<int8_t, true>(J, F, T, blocks, threads, lds_bytes, stream)
-                          : launch_run_f<int8_t, false>(J, F, T, blocks, threads, lds_bytes, stream);
-        case 2: return tr ? launch_run_f<int16_t, true>(J, F, T, blocks, threads, lds_bytes, stream)
-                          : launch_run_f<int16_t, false>(J, F, T, blocks, threads, lds_bytes, stream);
-        case 4: return tr ? launch_run_f<int32_t, true>(J, F, T, blocks, threads, lds_bytes, stream)
-                          : launch_run_f<int32_t, false>(J, F, T, blocks, threads, lds_bytes, stream);
+        case 1: return launch_run_w<int8_t>(J, F, pre, trace, blocks, threads, lds_bytes, stream);
+        case 2: return launch_run_w<int16_t>(J, F, pre, trace, blocks, threads, lds_bytes, stream);
+        case 4: return launch_run_w<int32_t>(J, F, pre, trace, blocks, threads, lds_bytes, stream);
         default: return (int)hipErrorInvalidValue;
     }
 }

@@ -59,6 +59,7 @@ struct StateBuf {
 
 // Launch shape of the step kernel.
 struct LaunchShape {
+    int pre = 1;        // random numbers one step ahead
     int F = 8;
     int NW = 1;
     int RPW = 1;
@@ -80,7 +81,11 @@ struct da_ctx {
     int32_t *d_b = nullptr;
     dapt::StateBuf st;
     hipStream_t own_stream = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;          // last call
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;  // calls since reset
+    size_t ev_used = 0;
+    double folded_ms = 0.0;      // calls since reset that left the pool
+    int64_t folded_calls = 0;
     da_kernel_stats last{};
     bool have_stats = false;
     std::string err;
@@ -100,10 +105,13 @@ void set_thread_error(const std::string &msg);
 int fail(da_ctx *ctx, int code, const std::string &msg);
 int check_hip(da_ctx *ctx, hipError_t e, const char *what);
 int validate_schedule(const da_schedule *s, std::string &err);
-LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch);
+LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch,
+                         bool anneal_mode);
 JobDesc make_job(const da_ctx *ctx, const LevelTables &lt, int32_t R, uint32_t rid_base,
                  uint64_t seed, int64_t steps, const da_schedule &s, const LaunchShape &sh);
 int init_state(da_ctx *ctx, const JobDesc &J, int init, hipStream_t stream);
+// Event pair for the next timed call (from the context's pool).
+int next_events(da_ctx *ctx, hipEvent_t &e0, hipEvent_t &e1);
 std::vector<double> schedule_temps(const da_schedule &s);
 
 }  // namespace dapt
