@@ -373,6 +373,8 @@ def da_submit(srv: Server, Q, sched: da_schedule, replicas: int, steps: int, see
 
 
 def _collect(fn, srv: Server, ticket: int):
+    if ticket not in srv._jobs:   # unknown here: let the library report it
+        _check(fn(srv.ptr, ctypes.c_uint64(ticket), None, None))
     R, N = srv._jobs[ticket]
     out = _host_outputs(R, N)
     res = _result_struct(out)

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -19,6 +20,17 @@ namespace dapt {
 namespace {
 thread_local std::string t_err;
 constexpr size_t kEventPool = 1024;
+
+int64_t gcd64(int64_t a, int64_t b) {
+    a = a < 0 ? -a : a;
+    b = b < 0 ? -b : b;
+    while (b) {
+        const int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
 }  // namespace
 
 void set_thread_error(const std::string &msg) { t_err = msg; }
@@ -121,11 +133,11 @@ LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch,
     sh.RPW = rpw;
     const int64_t w_bytes = (int64_t)ctx->N * ctx->ld * ctx->dtype;
     const int want = launch ? launch->w_in_lds : 0;
-    sh.w_lds = (want >= 0 && w_bytes <= (want > 0 ? 128 * 1024 : 64 * 1024)) ? 1 : 0;
+    sh.w_lds = (want >= 0 && w_bytes <= (want > 0 ? device_lds_limit() : 32 * 1024)) ? 1 : 0;
     sh.threads = 64 * sh.NW * sh.RPW;
     sh.blocks = (R + sh.RPW - 1) / sh.RPW;
     sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, sh.w_lds ? (int)w_bytes : 0, stage);
-    if (sh.lds > 160 * 1024 && sh.w_lds) {
+    if (sh.lds > (size_t)device_lds_limit() && sh.w_lds) {
         sh.w_lds = 0;
         sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0, stage);
     }
@@ -178,6 +190,182 @@ int init_state(da_ctx *ctx, const JobDesc &J, int init, hipStream_t stream) {
         if (!e) e = launch_energy_from_fields(J, J.x, J.h, J.R, J.E, true, stream);
     }
     return check_hip(ctx, (hipError_t)e, "state initialisation launch");
+}
+
+int device_lds_limit() {
+    static int limit = -1;
+    if (limit < 0) {
+        int dev = 0;
+        hipDeviceProp_t p;
+        limit = 64 * 1024;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess &&
+            p.sharedMemPerBlock > 0)
+            limit = (int)p.sharedMemPerBlock;
+    }
+    return limit;
+}
+
+LaunchShape batch_shape(const da_ctx *ctx) {
+    LaunchShape sh;
+    sh.pre = 0;
+    sh.F = 8;
+    sh.NW = (ctx->N + 511) / 512;
+    sh.RPW = 16 / sh.NW;
+    sh.w_lds = 0;
+    sh.threads = 1024;
+    sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0, 1);
+    return sh;
+}
+
+void append_batch_items(const JobDesc &J, int job_index, std::vector<BatchItem> &items) {
+    for (int32_t r0 = 0; r0 < J.R; r0 += J.RPW) items.push_back(BatchItem{job_index, r0});
+}
+
+int BatchRunner::prepare(std::string &err) {
+    if (exec) return DA_OK;
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    blocks = cus;
+    lds = 0;
+    for (int nw = 1; nw <= 16; ++nw) lds = std::max(lds, run_lds_bytes(nw, 16 / nw, 8, 0, 1));
+    if (hipMalloc(&d_jobs, sizeof(JobDesc) * kCapJobs) != hipSuccess ||
+        hipMalloc(&d_items, sizeof(BatchItem) * kCapItems) != hipSuccess ||
+        hipMalloc(&d_n, 4) != hipSuccess || hipMalloc(&d_counter, 4) != hipSuccess ||
+        hipHostMalloc(&h_jobs, sizeof(JobDesc) * kCapJobs) != hipSuccess ||
+        hipHostMalloc(&h_items, sizeof(BatchItem) * kCapItems) != hipSuccess ||
+        hipHostMalloc(&h_n, 4) != hipSuccess) {
+        err = "batch descriptor allocation failed";
+        release();
+        return DA_ENOMEM;
+    }
+    if (hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        err = "stream creation failed";
+        release();
+        return DA_EDEVICE;
+    }
+    // capture: counter reset (a fill kernel, no memset node) + persistent kernel
+    const char *stage = "begin capture";
+    hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        stage = "counter reset node";
+        e = (hipError_t)launch_fill_i32(d_counter, 0, 1, cap_stream);
+        if (e == hipSuccess) {
+            stage = "kernel node";
+            e = (hipError_t)launch_batch(d_jobs, d_items, d_n, d_counter, blocks, 1024, lds,
+                                         cap_stream);
+        }
+        const hipError_t e2 = hipStreamEndCapture(cap_stream, &graph);
+        if (e == hipSuccess) {
+            stage = "end capture";
+            e = e2;
+        }
+    }
+    if (e == hipSuccess) {
+        stage = "instantiate";
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    }
+    if (e != hipSuccess) {
+        err = std::string("batch graph capture failed at ") + stage + ": " + hipGetErrorString(e);
+        release();
+        return DA_EDEVICE;
+    }
+    return DA_OK;
+}
+
+int BatchRunner::run(const std::vector<JobDesc> &jobs, const std::vector<BatchItem> &items,
+                     hipStream_t s, std::string &err) {
+    int rc = prepare(err);
+    if (rc) return rc;
+    if (jobs.size() > (size_t)kCapJobs) {
+        err = "too many jobs in one batch";
+        return DA_EINVAL;
+    }
+    // longest items first so the tail of the persistent launch is short
+    std::vector<BatchItem> order(items);
+    std::stable_sort(order.begin(), order.end(), [&](const BatchItem &p, const BatchItem &q) {
+        const JobDesc &a = jobs[(size_t)p.job], &b = jobs[(size_t)q.job];
+        return (a.s1 - a.s0) * a.NW > (b.s1 - b.s0) * b.NW;
+    });
+    std::memcpy(h_jobs, jobs.data(), jobs.size() * sizeof(JobDesc));
+    for (size_t off = 0; off < order.size(); off += kCapItems) {
+        const size_t n = std::min(order.size() - off, (size_t)kCapItems);
+        // the previous chunk must be done with the tables before they change
+        if (off) {
+            hipError_t e = hipStreamSynchronize(s);
+            if (e != hipSuccess) {
+                err = hipGetErrorString(e);
+                return DA_EDEVICE;
+            }
+        }
+        std::memcpy(h_items, order.data() + off, n * sizeof(BatchItem));
+        *h_n = (int32_t)n;
+        hipError_t e = hipMemcpyAsync(d_jobs, h_jobs, jobs.size() * sizeof(JobDesc),
+                                      hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_items, h_items, n * sizeof(BatchItem), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_n, h_n, 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipGraphLaunch(exec, s);
+        if (e != hipSuccess) {
+            err = std::string("batch launch failed: ") + hipGetErrorString(e);
+            return DA_EDEVICE;
+        }
+    }
+    return DA_OK;
+}
+
+void BatchRunner::release() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (void *p : {(void *)d_jobs, (void *)d_items, (void *)d_n, (void *)d_counter})
+        if (p) (void)hipFree(p);
+    for (void *p : {(void *)h_jobs, (void *)h_items, (void *)h_n})
+        if (p) (void)hipHostFree(p);
+    exec = nullptr;
+    graph = nullptr;
+    cap_stream = nullptr;
+    d_jobs = nullptr;
+    d_items = nullptr;
+    d_n = d_counter = nullptr;
+    h_jobs = nullptr;
+    h_items = nullptr;
+    h_n = nullptr;
+}
+
+int derive_storage(const int32_t *Q, int32_t N, int32_t dtype_hint, int32_t &dtype,
+                   int32_t &wscale, std::string &err) {
+    const size_t n = (size_t)N;
+    int64_t g = 0, maxrow = 0, maxw = 0;
+    for (size_t i = 0; i < n; ++i) {
+        const int64_t bi = Q[i * n + i];
+        int64_t row = bi < 0 ? -bi : bi;
+        for (size_t j = 0; j < n; ++j) {
+            if (i == j) continue;
+            const int64_t w = (int64_t)Q[i * n + j] + (int64_t)Q[j * n + i];
+            const int64_t aw = w < 0 ? -w : w;
+            row += aw;
+            maxw = std::max(maxw, aw);
+            if (w) g = gcd64(g, w);
+        }
+        maxrow = std::max(maxrow, row);
+    }
+    if (maxrow > (int64_t(1) << 30)) {
+        err = "max_i |b_i| + sum_j |W_ij| exceeds 2^30: fields would not fit int32";
+        return DA_ERANGE;
+    }
+    if (g == 0) g = 1;
+    maxw /= g;
+    int dt = dtype_hint;
+    if (dt == DA_DTYPE_AUTO) dt = maxw <= 127 ? 1 : (maxw <= 32767 ? 2 : 4);
+    const int64_t lim = dt == 1 ? 127 : (dt == 2 ? 32767 : 2147483647);
+    if (maxw > lim) {
+        err = "couplings do not fit the requested type";
+        return DA_ERANGE;
+    }
+    dtype = dt;
+    wscale = (int32_t)g;
+    return DA_OK;
 }
 
 int next_events(da_ctx *ctx, hipEvent_t &e0, hipEvent_t &e1) {
@@ -233,17 +421,6 @@ bool device_is_gfx950(std::string &err) {
         return false;
     }
     return true;
-}
-
-int64_t gcd64(int64_t a, int64_t b) {
-    a = a < 0 ? -a : a;
-    b = b < 0 ? -b : b;
-    while (b) {
-        const int64_t t = a % b;
-        a = b;
-        b = t;
-    }
-    return a;
 }
 
 hipStream_t ctx_stream(da_ctx *ctx, void *stream) {
@@ -350,32 +527,11 @@ int da_create(const int32_t *Q, int32_t N, int32_t dtype_hint, da_ctx **out) {
     std::string err;
     if (!device_is_gfx950(err)) return fail(nullptr, DA_EDEVICE, err);
 
-    // W_ij = Q_ij + Q_ji off the diagonal, b_i = Q_ii (E = x^T Q x).
+    int32_t dtype = 0, wscale = 1;
+    int rc0 = derive_storage(Q, N, dtype_hint, dtype, wscale, err);
+    if (rc0) return fail(nullptr, rc0, err);
     const size_t n = (size_t)N;
-    std::vector<int64_t> W(n * n);
-    std::vector<int64_t> b(n);
-    int64_t g = 0, maxrow = 0;
-    for (size_t i = 0; i < n; ++i) {
-        b[i] = Q[i * n + i];
-        int64_t row = b[i] < 0 ? -b[i] : b[i];
-        for (size_t j = 0; j < n; ++j) {
-            const int64_t w = (i == j) ? 0 : (int64_t)Q[i * n + j] + (int64_t)Q[j * n + i];
-            W[i * n + j] = w;
-            row += w < 0 ? -w : w;
-            if (w) g = gcd64(g, w);
-        }
-        maxrow = std::max(maxrow, row);
-    }
-    if (maxrow > (int64_t(1) << 30))
-        return fail(nullptr, DA_ERANGE,
-                    "max_i |b_i| + sum_j |W_ij| exceeds 2^30: fields would not fit int32");
-    if (g == 0) g = 1;
-    int64_t maxw = 0;
-    for (auto w : W) maxw = std::max(maxw, (w < 0 ? -w : w) / g);
-    int dtype = dtype_hint;
-    if (dtype == DA_DTYPE_AUTO) dtype = maxw <= 127 ? 1 : (maxw <= 32767 ? 2 : 4);
-    const int64_t lim = dtype == 1 ? 127 : (dtype == 2 ? 32767 : 2147483647);
-    if (maxw > lim) return fail(nullptr, DA_ERANGE, "couplings do not fit the requested type");
+    const int64_t g = wscale;
 
     da_ctx *ctx = new (std::nothrow) da_ctx();
     if (!ctx) return fail(nullptr, DA_ENOMEM, "host allocation failed");
@@ -388,14 +544,15 @@ int da_create(const int32_t *Q, int32_t N, int32_t dtype_hint, da_ctx **out) {
     std::vector<uint8_t> Wd(ld * ld * (size_t)dtype, 0);
     for (size_t i = 0; i < n; ++i)
         for (size_t j = 0; j < n; ++j) {
-            const int64_t v = W[i * n + j] / g;
+            const int64_t w = (i == j) ? 0 : (int64_t)Q[i * n + j] + (int64_t)Q[j * n + i];
+            const int64_t v = w / g;
             void *dst = Wd.data() + (i * ld + j) * (size_t)dtype;
             if (dtype == 1) { int8_t t = (int8_t)v; std::memcpy(dst, &t, 1); }
             else if (dtype == 2) { int16_t t = (int16_t)v; std::memcpy(dst, &t, 2); }
             else { int32_t t = (int32_t)v; std::memcpy(dst, &t, 4); }
         }
     std::vector<int32_t> bd(ld, 0);
-    for (size_t i = 0; i < n; ++i) bd[i] = (int32_t)b[i];
+    for (size_t i = 0; i < n; ++i) bd[i] = Q[i * n + i];
     int rc = check_hip(nullptr, hipMalloc(&ctx->d_W, Wd.size()), "W allocation");
     if (!rc) rc = check_hip(nullptr, hipMalloc(&ctx->d_b, ld * 4), "b allocation");
     if (!rc) rc = check_hip(nullptr, hipMemcpy(ctx->d_W, Wd.data(), Wd.size(), hipMemcpyHostToDevice), "W upload");
@@ -500,7 +657,6 @@ int da_anneal_batch(const da_batch_item *items, int32_t count, void *stream) {
                 return fail(nullptr, DA_EINVAL, "batch items must use distinct contexts");
     std::vector<JobDesc> jobs((size_t)count);
     std::vector<BatchItem> work;
-    size_t lds = 0;
     std::vector<std::shared_ptr<LevelTables>> keep;
     for (int32_t a = 0; a < count; ++a) {
         const da_batch_item &it = items[a];
@@ -518,62 +674,35 @@ int da_anneal_batch(const da_batch_item *items, int32_t count, void *stream) {
         keep.push_back(lt);
         ctx->keep_tables = lt;
         if (!ctx->st.ensure(it.replicas, ctx->ld, err)) return fail(ctx, DA_ENOMEM, err);
-        // every workgroup of the persistent launch has 16 waves
-        da_launch shape_req{8, 16, -1, -1};
-        LaunchShape sh = choose_shape(ctx, it.replicas, &shape_req, true);
-        sh.RPW = 16 / sh.NW;
-        sh.w_lds = 0;
-        sh.pre = 0;
-        sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0, 1);
-        if (sh.F != 8) return fail(ctx, DA_EINVAL, "batched launch needs N <= 8192");
-        lds = std::max(lds, sh.lds);
+        const LaunchShape sh = batch_shape(ctx);
         jobs[(size_t)a] = make_job(ctx, *lt, it.replicas, (uint32_t)it.replica_base, it.seed,
                                    it.steps, it.schedule, sh);
         rc = init_state(ctx, jobs[(size_t)a], it.schedule.init, s);
         if (rc) return rc;
-        if (it.steps > 0)
-            for (int32_t r0 = 0; r0 < it.replicas; r0 += sh.RPW) work.push_back(BatchItem{a, r0});
+        if (it.steps > 0) append_batch_items(jobs[(size_t)a], a, work);
         record_stats(ctx, sh, 1);
     }
-    // longest jobs first so the tail of the persistent launch is short
-    std::stable_sort(work.begin(), work.end(), [&](const BatchItem &p, const BatchItem &q) {
-        const int64_t cp = jobs[(size_t)p.job].S * jobs[(size_t)p.job].NW;
-        const int64_t cq = jobs[(size_t)q.job].S * jobs[(size_t)q.job].NW;
-        return cp > cq;
-    });
     da_ctx *c0 = items[0].ctx;
-    JobDesc *d_jobs = nullptr;
-    BatchItem *d_items = nullptr;
-    int32_t *d_counter = nullptr;
-    int rc = check_hip(c0, hipMalloc(&d_jobs, jobs.size() * sizeof(JobDesc)), "batch allocation");
-    if (!rc) rc = check_hip(c0, hipMalloc(&d_items, std::max<size_t>(work.size(), 1) * sizeof(BatchItem)), "batch allocation");
-    if (!rc) rc = check_hip(c0, hipMalloc(&d_counter, 4), "batch allocation");
-    if (!rc) rc = check_hip(c0, hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * sizeof(JobDesc), hipMemcpyHostToDevice, s), "batch upload");
-    if (!rc && !work.empty()) rc = check_hip(c0, hipMemcpyAsync(d_items, work.data(), work.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s), "batch upload");
-    if (!rc) rc = check_hip(c0, (hipError_t)launch_fill_i32(d_counter, 0, 1, s), "counter reset");
+    // process-lifetime runner (never destroyed: no device frees at exit)
+    static std::mutex runner_mu;
+    static BatchRunner *runner_p = new BatchRunner();
+    BatchRunner &runner = *runner_p;
+    std::lock_guard<std::mutex> lock(runner_mu);
+    std::string err;
     hipEvent_t be0 = nullptr, be1 = nullptr;
-    if (!rc) rc = next_events(c0, be0, be1);
+    int rc = next_events(c0, be0, be1);
     if (!rc) rc = check_hip(c0, hipEventRecord(be0, s), "event record");
     if (!rc && !work.empty()) {
-        int dev = 0, cus = 256;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        const int per_cu = lds > 80 * 1024 ? 1 : 2;
-        const int blocks = (int)std::min<size_t>(work.size(), (size_t)cus * per_cu);
-        rc = check_hip(c0, (hipError_t)launch_batch(d_jobs, d_items, (int)work.size(), d_counter,
-                                                      blocks, 1024, lds, s),
-                       "batch kernel launch");
-        c0->last.blocks = blocks;
+        rc = runner.run(jobs, work, s, err);
+        if (rc) fail(c0, rc, err);
+        c0->last.blocks = runner.blocks;
         c0->last.threads = 1024;
     }
     if (!rc) rc = check_hip(c0, hipEventRecord(be1, s), "event record");
     for (int32_t a = 0; a < count && !rc; ++a)
         rc = extract_outputs(items[a].ctx, jobs[(size_t)a], items[a].replicas, &items[a].out_dev, s);
-    // the device tables of the batch must outlive the kernel
-    (void)hipStreamSynchronize(s);
-    if (d_jobs) (void)hipFree(d_jobs);
-    if (d_items) (void)hipFree(d_items);
-    if (d_counter) (void)hipFree(d_counter);
+    // descriptor tables are reused by the next batch: finish this one first
+    if (!rc) rc = check_hip(c0, hipStreamSynchronize(s), "stream synchronise");
     return rc;
 }
 

@@ -72,8 +72,8 @@ struct TraceDesc {
     int64_t stride;        // steps per replica row
 };
 
-// Work item of the batched persistent kernel: `count` replica slots of job
-// `job` starting at state row `r0`.
+// Work item of the batched persistent kernel: the replicas of job `job` that
+// one workgroup runs, starting at state row `r0` (RPW of them).
 struct BatchItem {
     int32_t job;
     int32_t r0;
@@ -89,7 +89,9 @@ int launch_energy_from_fields(const JobDesc &J, const uint8_t *X, const int32_t 
                               int64_t *E_out, bool finish_state, void *stream);
 int launch_run(const JobDesc &J, int F, bool pre, const TraceDesc *trace, int blocks, int threads,
                size_t lds_bytes, void *stream);
-int launch_batch(const JobDesc *jobs_dev, const BatchItem *items_dev, int n_items,
+// Persistent batched step kernel; the item count is read from device memory so
+// one captured graph can serve batches of any size.
+int launch_batch(const JobDesc *jobs_dev, const BatchItem *items_dev, const int32_t *n_items_dev,
                  int32_t *counter_dev, int blocks, int threads, size_t lds_bytes, void *stream);
 int launch_pt_exchange(int64_t *E, int32_t *slot2rep, int32_t *lvl_of_rep, const double *dbeta,
                        const double *lnU, int32_t M, int32_t chains, uint64_t seed,
@@ -100,6 +102,9 @@ int launch_extract(const JobDesc &J, const uint8_t *src_x, uint8_t *dst_x, int32
                    void *stream);
 int launch_copy_i64(const int64_t *src, int64_t *dst, int32_t n, void *stream);
 int launch_fill_i32(int32_t *dst, int32_t value, int64_t n, void *stream);
+
+// Dynamic LDS a workgroup may use on the current device (bytes).
+int device_lds_limit();
 
 // Workgroup LDS bytes the run kernel needs for a launch shape (stage_brk: the
 // level's bracket table is staged in LDS, anneal mode).

@@ -497,11 +497,12 @@ __global__ __launch_bounds__(1024) void k_run(JobDesc J, TraceDesc T) {
 // launch's workgroup size; jobs of any size and coupling type mix freely.
 template <int F>
 __global__ __launch_bounds__(1024) void k_batch(const JobDesc *__restrict__ jobs,
-                                                const BatchItem *__restrict__ items, int n_items,
-                                                int32_t *counter) {
+                                                const BatchItem *__restrict__ items,
+                                                const int32_t *n_items_ptr, int32_t *counter) {
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ int item_id;
     const TraceDesc T{nullptr, nullptr, nullptr, 0};
+    const int n_items = *n_items_ptr;
     for (;;) {
         if (threadIdx.x == 0) item_id = atomicAdd(counter, 1);
         __syncthreads();
@@ -732,14 +733,6 @@ inline int grid_for(int64_t n, int threads) {
 template <typename WT, int F, bool TRACE, bool PRE>
 int launch_run_t(const JobDesc &J, const TraceDesc &T, int blocks, int threads, size_t lds,
                  void *stream) {
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_run<WT, F, TRACE, PRE, true>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_run<WT, F, TRACE, PRE, false>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr_set = true;
-    }
     if (J.lvl_of_rep)
         hipLaunchKernelGGL((k_run<WT, F, TRACE, PRE, false>), dim3(blocks), dim3(threads), lds,
                            S(stream), J, T);
@@ -783,16 +776,10 @@ int launch_run(const JobDesc &J, int F, bool pre, const TraceDesc *trace, int bl
     }
 }
 
-int launch_batch(const JobDesc *jobs_dev, const BatchItem *items_dev, int n_items,
+int launch_batch(const JobDesc *jobs_dev, const BatchItem *items_dev, const int32_t *n_items_dev,
                  int32_t *counter_dev, int blocks, int threads, size_t lds_bytes, void *stream) {
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch<8>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr_set = true;
-    }
     hipLaunchKernelGGL((k_batch<8>), dim3(blocks), dim3(threads), lds_bytes, S(stream), jobs_dev,
-                       items_dev, n_items, counter_dev);
+                       items_dev, n_items_dev, counter_dev);
     return (int)hipGetLastError();
 }
 

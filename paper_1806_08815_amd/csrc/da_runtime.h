@@ -69,6 +69,44 @@ struct LaunchShape {
     size_t lds = 0;
 };
 
+// Runs batches of jobs in one persistent launch of the batched step kernel.
+// Descriptor tables have a fixed device capacity so that the launch (counter
+// reset + kernel) is captured once as a hipGraph and replayed for every batch;
+// only the table contents are re-uploaded, from pinned host staging.
+struct BatchRunner {
+    static constexpr int kCapJobs = 1024;
+    static constexpr int kCapItems = 65536;
+    JobDesc *d_jobs = nullptr;
+    BatchItem *d_items = nullptr;
+    int32_t *d_n = nullptr;
+    int32_t *d_counter = nullptr;
+    JobDesc *h_jobs = nullptr;       // pinned
+    BatchItem *h_items = nullptr;    // pinned
+    int32_t *h_n = nullptr;          // pinned
+    int blocks = 0;
+    size_t lds = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int prepare(std::string &err);
+    // Enqueues the batch on `s` (jobs must already have initialised state).
+    int run(const std::vector<JobDesc> &jobs, const std::vector<BatchItem> &items, hipStream_t s,
+            std::string &err);
+    void release();
+    ~BatchRunner() { release(); }
+};
+
+// Launch shape of a job inside the batched kernel (16 waves per workgroup).
+LaunchShape batch_shape(const da_ctx *ctx);
+// The workgroup items of one job, appended to `items`.
+void append_batch_items(const JobDesc &J, int job_index, std::vector<BatchItem> &items);
+
+// Storage choice for a Q (shared by da_create and admission): W = Q + Q^T off
+// the diagonal, b = diag(Q); returns DA_OK and fills dtype / wscale, or an
+// error code with `err` set.
+int derive_storage(const int32_t *Q, int32_t N, int32_t dtype_hint, int32_t &dtype,
+                   int32_t &wscale, std::string &err);
+
 }  // namespace dapt
 
 struct da_ctx {

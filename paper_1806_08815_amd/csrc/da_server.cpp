@@ -1,16 +1,378 @@
-// da_server.cpp -- continuous-batching server (entry points; not yet running jobs).
+// da_server.cpp -- continuous-batching solve server.
+//
+// Jobs are submitted from any thread.  One worker thread owns the device:
+//   * admission: queued jobs are admitted first-fit, in arrival order, while
+//     their device footprint (da_job_footprint) fits the free budget; an
+//     admitted job gets its own context (coupling matrix, fields, states and
+//     tables stay resident on the device until it finishes);
+//   * epochs: every resident job advances by up to epoch_steps Monte Carlo
+//     steps, all of them together in one persistent launch of the batched
+//     step kernel (replayed from a captured graph);
+//   * retirement: jobs that reached their step count are copied to host
+//     buffers and their device memory is released, which lets waiting jobs in
+//     at the next epoch boundary.
+// The step kernel resumes exactly where an epoch stopped and every random
+// number is keyed by (seed, job-local replica id, global step), so a job's
+// results are the same alone, in any mix, and as a plain da_anneal call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <set>
+#include <thread>
+#include <vector>
+
 #include "da_runtime.h"
 
 using namespace dapt;
 
+namespace {
+
+constexpr int64_t kDefaultEpochSteps = 8192;
+
+struct Job {
+    uint64_t ticket = 0;
+    std::vector<int32_t> Q;
+    da_job spec{};
+    int32_t dtype = 0, wscale = 1;
+    int64_t footprint = 0;
+    da_ctx *ctx = nullptr;
+    std::shared_ptr<LevelTables> tables;
+    JobDesc J{};
+    int64_t done_steps = 0;
+    int status = DA_OK;
+    std::string err;
+    // results
+    std::vector<uint8_t> best_x, final_x;
+    std::vector<int64_t> best_E, final_E, n_accept;
+    da_job_stats stats{};
+};
+
+double now_s(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+struct da_server {
+    size_t budget = 0;
+    int64_t epoch_steps = kDefaultEpochSteps;
+    int32_t max_resident = 0;
+    int device = 0;
+    std::chrono::steady_clock::time_point t0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<std::unique_ptr<Job>> queue;
+    std::vector<std::unique_ptr<Job>> resident;
+    std::map<uint64_t, std::unique_ptr<Job>> finished;
+    std::set<uint64_t> retiring;   // left `resident`, results being copied out
+    uint64_t next_ticket = 1;
+    int64_t used = 0;
+    bool stop = false;
+    std::thread worker;
+    hipStream_t stream = nullptr;
+    BatchRunner runner;
+
+    void run();
+    bool admit_locked(std::vector<Job *> &admitted);
+    int start_job(Job &j);
+    void retire(std::unique_ptr<Job> &j);
+};
+
+extern "C" int64_t da_job_footprint(int32_t N, int32_t dtype_bytes, int32_t replicas,
+                                    int32_t n_levels) {
+    if (N < 1 || replicas < 1 || n_levels < 1 || (dtype_bytes != 1 && dtype_bytes != 2 &&
+                                                   dtype_bytes != 4))
+        return -1;
+    const int64_t ld = ((int64_t)N + 63) / 64 * 64;
+    const int64_t w = ld * ld * dtype_bytes + ld * 4;
+    const int64_t state = StateBuf::bytes_for(replicas, (int32_t)ld);
+    const int64_t tables = level_table_bytes(n_levels, (int64_t)n_levels * kMaxBuckets);
+    const int64_t out = (int64_t)replicas * N * 2 + (int64_t)replicas * 8 * 3;
+    return w + state + tables + out;
+}
+
+// Creates the job's context, tables and initial state on the server stream.
+int da_server::start_job(Job &j) {
+    da_ctx *ctx = nullptr;
+    int rc = da_create(j.Q.data(), j.spec.N, j.spec.dtype_hint, &ctx);
+    if (rc) {
+        j.err = da_last_error(nullptr);
+        return rc;
+    }
+    j.ctx = ctx;
+    j.tables = get_level_tables(schedule_temps(j.spec.schedule), j.err);
+    if (!j.tables) return DA_ENOMEM;
+    ctx->keep_tables = j.tables;
+    if (!ctx->st.ensure(j.spec.replicas, ctx->ld, j.err)) return DA_ENOMEM;
+    const LaunchShape sh = batch_shape(ctx);
+    j.J = make_job(ctx, *j.tables, j.spec.replicas, 0u, j.spec.seed, j.spec.steps,
+                   j.spec.schedule, sh);
+    rc = init_state(ctx, j.J, j.spec.schedule.init, stream);
+    if (rc) j.err = ctx->err;
+    return rc;
+}
+
+bool da_server::admit_locked(std::vector<Job *> &admitted) {
+    bool any = false;
+    for (auto it = queue.begin(); it != queue.end();) {
+        if (max_resident > 0 && (int32_t)(resident.size() + admitted.size()) >= max_resident) break;
+        if ((*it)->footprint <= (int64_t)budget - used) {
+            used += (*it)->footprint;
+            (*it)->stats.t_admit = now_s(t0);
+            admitted.push_back(it->get());
+            resident.push_back(std::move(*it));
+            it = queue.erase(it);
+            any = true;
+        } else {
+            ++it;
+        }
+    }
+    return any;
+}
+
+void da_server::retire(std::unique_ptr<Job> &jp) {
+    Job &j = *jp;
+    if (j.status == DA_OK && j.ctx) {
+        const size_t R = (size_t)j.spec.replicas, N = (size_t)j.spec.N, ld = (size_t)j.J.ld;
+        j.best_x.resize(R * N);
+        j.final_x.resize(R * N);
+        j.best_E.resize(R);
+        j.final_E.resize(R);
+        j.n_accept.resize(R);
+        hipError_t e = hipMemcpy2DAsync(j.best_x.data(), N, j.J.bx, ld, N, R,
+                                        hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess)
+            e = hipMemcpy2DAsync(j.final_x.data(), N, j.J.x, ld, N, R, hipMemcpyDeviceToHost,
+                                 stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(j.best_E.data(), j.J.bE, R * 8, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(j.final_E.data(), j.J.E, R * 8, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(j.n_accept.data(), j.J.nacc, R * 8, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) {
+            j.status = DA_EDEVICE;
+            j.err = hipGetErrorString(e);
+        }
+    }
+    if (j.ctx) da_destroy(j.ctx);
+    j.ctx = nullptr;
+    j.tables.reset();
+    j.stats.t_done = now_s(t0);
+}
+
+void da_server::run() {
+    (void)hipSetDevice(device);
+    for (;;) {
+        std::vector<Job *> admitted;
+        {
+            std::unique_lock<std::mutex> lock(mu);
+            cv_work.wait(lock, [&] { return stop || !queue.empty() || !resident.empty(); });
+            if (stop) {
+                for (auto &q : queue) {
+                    q->status = DA_ENOTFOUND;
+                    q->err = "server shut down before the job was admitted";
+                }
+                queue.clear();
+                if (resident.empty()) break;
+            }
+            admit_locked(admitted);
+        }
+        for (Job *j : admitted) {
+            j->status = start_job(*j);
+            j->stats.device_bytes = j->footprint;
+        }
+        // one epoch over every resident job
+        std::vector<JobDesc> jobs;
+        std::vector<BatchItem> items;
+        std::vector<Job *> in_epoch;
+        {
+            std::lock_guard<std::mutex> lock(mu);
+            for (auto &jp : resident) {
+                Job &j = *jp;
+                if (j.status != DA_OK || j.done_steps >= j.spec.steps) continue;
+                JobDesc J = j.J;
+                J.s0 = j.done_steps;
+                J.s1 = std::min(j.spec.steps, j.done_steps + epoch_steps);
+                append_batch_items(J, (int)jobs.size(), items);
+                jobs.push_back(J);
+                in_epoch.push_back(&j);
+            }
+        }
+        if (!jobs.empty()) {
+            std::string err;
+            int rc = runner.run(jobs, items, stream, err);
+            if (rc == DA_OK) {
+                const hipError_t e = hipStreamSynchronize(stream);
+                if (e != hipSuccess) {
+                    rc = DA_EDEVICE;
+                    err = hipGetErrorString(e);
+                }
+            }
+            for (size_t a = 0; a < in_epoch.size(); ++a) {
+                Job &j = *in_epoch[a];
+                if (rc) {
+                    j.status = rc;
+                    j.err = err;
+                } else {
+                    j.done_steps = jobs[a].s1;
+                    j.stats.epochs += 1;
+                }
+            }
+        }
+        // retire finished (or failed) jobs and wake their waiters
+        std::vector<std::unique_ptr<Job>> leaving;
+        {
+            std::lock_guard<std::mutex> lock(mu);
+            for (auto it = resident.begin(); it != resident.end();) {
+                if ((*it)->status != DA_OK || (*it)->done_steps >= (*it)->spec.steps) {
+                    retiring.insert((*it)->ticket);
+                    leaving.push_back(std::move(*it));
+                    it = resident.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+        }
+        for (auto &jp : leaving) retire(jp);
+        if (!leaving.empty()) {
+            std::lock_guard<std::mutex> lock(mu);
+            for (auto &jp : leaving) {
+                used -= jp->footprint;
+                const uint64_t t = jp->ticket;
+                retiring.erase(t);
+                finished[t] = std::move(jp);
+            }
+            cv_done.notify_all();
+        }
+    }
+    cv_done.notify_all();
+}
+
 extern "C" {
-int da_server_create(size_t, const da_server_opts *, da_server **out) {
-    if (out) *out = nullptr;
-    return fail(nullptr, DA_EINVAL, "server not available in this build");
+
+int da_server_create(size_t hbm_budget, const da_server_opts *opts, da_server **out) {
+    if (!out) return fail(nullptr, DA_EINVAL, "out is null");
+    *out = nullptr;
+    if (hbm_budget == 0) return fail(nullptr, DA_EINVAL, "hbm_budget must be > 0");
+    auto *srv = new (std::nothrow) da_server();
+    if (!srv) return fail(nullptr, DA_ENOMEM, "host allocation failed");
+    srv->budget = hbm_budget;
+    if (opts && opts->epoch_steps > 0) srv->epoch_steps = opts->epoch_steps;
+    srv->max_resident = BatchRunner::kCapJobs;
+    if (opts && opts->max_resident > 0)
+        srv->max_resident = std::min<int32_t>(opts->max_resident, BatchRunner::kCapJobs);
+    srv->t0 = std::chrono::steady_clock::now();
+    (void)hipGetDevice(&srv->device);
+    if (hipStreamCreateWithFlags(&srv->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete srv;
+        return fail(nullptr, DA_EDEVICE, "server stream creation failed");
+    }
+    std::string err;
+    const int rc = srv->runner.prepare(err);
+    if (rc) {
+        (void)hipStreamDestroy(srv->stream);
+        delete srv;
+        return fail(nullptr, rc, err);
+    }
+    srv->worker = std::thread([srv] { srv->run(); });
+    *out = srv;
+    return DA_OK;
 }
-int da_submit(da_server *, const da_job *, uint64_t *) { return fail(nullptr, DA_EINVAL, "no server"); }
-int da_poll(da_server *, uint64_t, da_result *, da_job_stats *) { return fail(nullptr, DA_ENOTFOUND, "no server"); }
-int da_wait(da_server *, uint64_t, da_result *, da_job_stats *) { return fail(nullptr, DA_ENOTFOUND, "no server"); }
-int64_t da_job_footprint(int32_t, int32_t, int32_t, int32_t) { return -1; }
-void da_server_destroy(da_server *) {}
+
+int da_submit(da_server *srv, const da_job *job, uint64_t *ticket) {
+    if (!srv || !job || !ticket || !job->Q) return fail(nullptr, DA_EINVAL, "null argument");
+    if (job->N < 1 || job->N > DA_MAX_N) return fail(nullptr, DA_EINVAL, "N must be in [1, 8192]");
+    if (job->replicas < 1 || job->steps < 0 || job->steps >= (int64_t(1) << 31))
+        return fail(nullptr, DA_EINVAL, "bad replicas or steps");
+    std::string err;
+    int rc = validate_schedule(&job->schedule, err);
+    if (rc) return fail(nullptr, rc, err);
+    auto j = std::make_unique<Job>();
+    rc = derive_storage(job->Q, job->N, job->dtype_hint, j->dtype, j->wscale, err);
+    if (rc) return fail(nullptr, rc, err);
+    j->footprint = da_job_footprint(job->N, j->dtype, job->replicas, job->schedule.n_levels);
+    if (j->footprint > (int64_t)srv->budget)
+        return fail(nullptr, DA_ENOMEM, "job alone exceeds the server's device budget");
+    j->spec = *job;
+    j->Q.assign(job->Q, job->Q + (size_t)job->N * job->N);
+    j->spec.Q = j->Q.data();
+    {
+        std::lock_guard<std::mutex> lock(srv->mu);
+        j->ticket = srv->next_ticket++;
+        j->stats.t_submit = now_s(srv->t0);
+        *ticket = j->ticket;
+        srv->queue.push_back(std::move(j));
+    }
+    srv->cv_work.notify_one();
+    return DA_OK;
 }
+
+static int collect(da_server *srv, uint64_t ticket, da_result *out, da_job_stats *stats,
+                   bool wait) {
+    if (!srv) return fail(nullptr, DA_EINVAL, "server is null");
+    std::unique_ptr<Job> j;
+    {
+        std::unique_lock<std::mutex> lock(srv->mu);
+        auto known = [&] {
+            if (srv->finished.count(ticket) || srv->retiring.count(ticket)) return true;
+            for (auto &q : srv->queue)
+                if (q->ticket == ticket) return true;
+            for (auto &q : srv->resident)
+                if (q->ticket == ticket) return true;
+            return false;
+        };
+        if (!known()) return fail(nullptr, DA_ENOTFOUND, "unknown or already collected ticket");
+        if (wait) {
+            srv->cv_done.wait(lock, [&] { return srv->finished.count(ticket) > 0 || !known(); });
+        }
+        auto it = srv->finished.find(ticket);
+        if (it == srv->finished.end()) {
+            if (!known()) return fail(nullptr, DA_ENOTFOUND, "job was dropped");
+            return DA_ENOTREADY;
+        }
+        j = std::move(it->second);
+        srv->finished.erase(it);
+    }
+    if (stats) *stats = j->stats;
+    if (j->status != DA_OK) return fail(nullptr, j->status, j->err);
+    if (out) {
+        if (out->best_x) std::memcpy(out->best_x, j->best_x.data(), j->best_x.size());
+        if (out->final_x) std::memcpy(out->final_x, j->final_x.data(), j->final_x.size());
+        if (out->best_E) std::memcpy(out->best_E, j->best_E.data(), j->best_E.size() * 8);
+        if (out->final_E) std::memcpy(out->final_E, j->final_E.data(), j->final_E.size() * 8);
+        if (out->n_accept) std::memcpy(out->n_accept, j->n_accept.data(), j->n_accept.size() * 8);
+    }
+    return DA_OK;
+}
+
+int da_poll(da_server *srv, uint64_t ticket, da_result *out, da_job_stats *stats) {
+    return collect(srv, ticket, out, stats, false);
+}
+
+int da_wait(da_server *srv, uint64_t ticket, da_result *out, da_job_stats *stats) {
+    return collect(srv, ticket, out, stats, true);
+}
+
+void da_server_destroy(da_server *srv) {
+    if (!srv) return;
+    {
+        std::lock_guard<std::mutex> lock(srv->mu);
+        srv->stop = true;
+    }
+    srv->cv_work.notify_all();
+    if (srv->worker.joinable()) srv->worker.join();
+    srv->runner.release();
+    if (srv->stream) (void)hipStreamDestroy(srv->stream);
+    delete srv;
+}
+
+}  // extern "C"

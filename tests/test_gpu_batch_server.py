@@ -1,0 +1,137 @@
+"""Batched persistent launches and the continuous-batching server on the GPU.
+
+A job's results must not depend on what it is batched or served with: every
+random number is keyed by (seed, job-local replica, step) and the step kernel
+resumes exactly at epoch boundaries.  So each job here is compared bit-exactly
+with the same job run alone through da_anneal, and small jobs with the oracle.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1806_08815_amd import instances
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("best_x", "best_E", "final_x", "final_E", "n_accept")
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_1806_08815_amd import api as a
+    a.lib()
+    return a
+
+
+def _job(kind, N, seed):
+    if kind == "sk":
+        Q = instances.ising_to_qubo(instances.sk_bimodal(N, seed))[0]
+        sc = max(1.0, N ** 0.5)
+        return Q, dict(T_hi=3.0 * sc, T_lo=0.05 * sc, eoff_inc=1)
+    Q = instances.ising_to_qubo(instances.sk_gaussian(N, seed, scale=2**16))[0]
+    return Q, dict(T_hi=3.0 * 2**16, T_lo=0.05 * 2**16, eoff_inc=2**16)
+
+
+SPECS = [  # kind, N, replicas, steps, init, dtype hint, n_levels
+    ("sk", 64, 16, 3000, "zeros", 0, 128),
+    ("gauss", 100, 7, 2500, "random", 0, 64),
+    ("sk", 300, 33, 1500, "zeros", 2, 128),
+    ("gauss", 1000, 5, 1200, "zeros", 4, 32),
+    ("sk", 1024, 20, 900, "random", 0, 128),
+    ("sk", 2000, 3, 700, "zeros", 0, 16),
+    ("gauss", 513, 17, 1000, "random", 0, 50),
+]
+
+
+def test_batch_matches_alone(api):
+    import torch
+    ctxs, items, alone = [], [], []
+    for a, (kind, N, R, S, init, hint, L) in enumerate(SPECS):
+        Q, t = _job(kind, N, 10 + a)
+        ctx = api.da_create(Q, hint)
+        sch = api.schedule(t["T_hi"], t["T_lo"], "geometric", L, t["eoff_inc"], init)
+        alone.append(api.da_anneal(ctx, sch, R, S, 100 + a))
+        ctxs.append(ctx)
+        items.append(dict(ctx=ctx, schedule=sch, replica_base=0, replicas=R, steps=S,
+                          seed=100 + a, out_dev=api.device_outputs(R, N)))
+    api.da_anneal_batch(items)
+    torch.cuda.synchronize()
+    for a, it in enumerate(items):
+        for k in KEYS:
+            got = it["out_dev"][k].cpu().numpy()
+            assert np.array_equal(got, alone[a][k]), (SPECS[a], k)
+    # and the oracle for the small ones
+    for a in (0, 1):
+        kind, N, R, S, init, hint, L = SPECS[a]
+        Q, t = _job(kind, N, 10 + a)
+        ref = oracle.anneal(Q, T_hi=t["T_hi"], T_lo=t["T_lo"], n_levels=L,
+                            eoff_inc=t["eoff_inc"], init=0 if init == "zeros" else 1,
+                            replicas=R, steps=S, seed=100 + a)
+        for k in KEYS:
+            assert np.array_equal(items[a]["out_dev"][k].cpu().numpy(), ref[k]), (a, k)
+
+
+def test_server_results_equal_alone(api):
+    # a budget that holds only some jobs at once forces queueing and admission
+    # as memory frees up; an epoch that does not divide the step counts forces
+    # resumption at arbitrary steps
+    specs = SPECS + [("sk", 128, 40, 2000, "zeros", 0, 128), ("gauss", 64, 9, 3100, "zeros", 0, 8)]
+    foot = [api.da_job_footprint(N, 4, R, L) for (_, N, R, _, _, _, L) in specs]
+    srv = api.da_server_create(int(max(foot) * 2.2), epoch_steps=777)
+    tickets, want = [], []
+    for a, (kind, N, R, S, init, hint, L) in enumerate(specs):
+        Q, t = _job(kind, N, 40 + a)
+        sch = api.schedule(t["T_hi"], t["T_lo"], "geometric", L, t["eoff_inc"], init)
+        ctx = api.da_create(Q, hint)
+        want.append(api.da_anneal(ctx, sch, R, S, 7 + a))
+        ctx.close()
+        tickets.append(api.da_submit(srv, Q, sch, R, S, 7 + a, hint))
+    got = [api.da_wait(srv, t) for t in tickets]
+    for a in range(len(specs)):
+        for k in KEYS:
+            assert np.array_equal(got[a][k], want[a][k]), (specs[a], k)
+        st = got[a]["stats"]
+        assert st["t_submit"] <= st["t_admit"] <= st["t_done"]
+        assert st["epochs"] == -(-specs[a][3] // 777)
+    # somebody had to wait for memory
+    assert max(g["stats"]["t_admit"] - g["stats"]["t_submit"] for g in got) > 0
+    srv.close()
+
+
+def test_server_tickets_and_admission(api):
+    Q, t = _job("sk", 256, 3)
+    sch = api.schedule(t["T_hi"], t["T_lo"], "geometric", 16, 1)
+    fp = api.da_job_footprint(256, 1, 64, 16)
+    assert fp > 256 * 256
+    assert api.da_job_footprint(512, 1, 64, 16) > fp
+    assert api.da_job_footprint(256, 4, 64, 16) > fp
+    srv = api.da_server_create(fp + 1024, epoch_steps=500)
+    with pytest.raises(api.DaError) as e:
+        api.da_submit(srv, Q, sch, 65_000, 10, 1)
+    assert e.value.code == api.DA_ENOMEM
+    t1 = api.da_submit(srv, Q, sch, 64, 20_000, 1)
+    t2 = api.da_submit(srv, Q, sch, 64, 1_000, 2)   # waits for t1's memory
+    r2 = api.da_wait(srv, t2)
+    r1 = api.da_wait(srv, t1)
+    assert r2["stats"]["t_admit"] >= r1["stats"]["t_done"] - 1e-6
+    with pytest.raises(api.DaError) as e:
+        api.da_wait(srv, t1)
+    assert e.value.code == api.DA_ENOTFOUND
+    srv.close()
+
+
+def test_server_poll_not_ready(api):
+    Q, t = _job("sk", 1024, 5)
+    sch = api.schedule(t["T_hi"], t["T_lo"], "geometric", 16, 1)
+    srv = api.da_server_create(1 << 34, epoch_steps=2000)
+    tk = api.da_submit(srv, Q, sch, 256, 40_000, 1)
+    assert api.da_poll(srv, tk) is None
+    t0 = time.time()
+    while api.da_poll(srv, tk) is None:
+        assert time.time() - t0 < 120
+        time.sleep(0.01)
+    srv.close()

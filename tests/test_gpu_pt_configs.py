@@ -1,0 +1,129 @@
+"""Parallel tempering and the full-size workloads on the GPU against the oracle.
+
+PT (Sec. II.D, exchange move of Algorithm 3) runs its exchanges on the device;
+the per-replica outputs, final temperature slots and swap counts must equal
+the oracle's.  At full workload sizes the oracle replays sampled replicas one
+by one (the counter-based random numbers make any replica replayable alone);
+the GPU runs the whole workload in the launch shape the benchmark times.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1806_08815_amd import instances, workloads
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("best_x", "best_E", "final_x", "final_E", "n_accept")
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_1806_08815_amd import api as a
+    a.lib()
+    return a
+
+
+@pytest.mark.parametrize("N,M,chains,rounds,K,inc", [
+    (64, 8, 3, 10, 64, 0), (200, 5, 2, 70, 16, 1), (700, 4, 1, 6, 100, 3), (1024, 32, 2, 3, 1024, 0),
+])
+def test_pt_parity(api, N, M, chains, rounds, K, inc):
+    Q = instances.ising_to_qubo(instances.sk_bimodal(N, N))[0]
+    temps = workloads.pt_temperatures(M, 0.1, 3.0, scale=N ** 0.5)
+    ctx = api.da_create(Q)
+    gpu = api.da_pt(ctx, temps, chains, rounds, K, inc, 5)
+    ref = oracle.pt(Q, temps, chains=chains, rounds=rounds, steps_per_round=K, eoff_inc=inc,
+                    seed=5)
+    for k in KEYS + ("slot", "n_swaps"):
+        assert np.array_equal(gpu[k], ref[k]), k
+    if M >= 5:
+        assert ref["n_swaps"].sum() > 0   # the exchange path was exercised
+
+
+def test_pt_gaussian_parity(api):
+    N, M = 300, 6
+    Q = instances.ising_to_qubo(instances.sk_gaussian(N, 3, scale=2**16))[0]
+    temps = workloads.pt_temperatures(M, 0.1, 3.0, scale=2**16)
+    ctx = api.da_create(Q)
+    gpu = api.da_pt(ctx, temps, 2, 8, 200, 2**16, 9)
+    ref = oracle.pt(Q, temps, chains=2, rounds=8, steps_per_round=200, eoff_inc=2**16, seed=9)
+    for k in KEYS + ("slot", "n_swaps"):
+        assert np.array_equal(gpu[k], ref[k]), k
+
+
+def _sampled(api, name, rows, dtype=None, launch=None):
+    w = workloads.WORKLOADS[name]
+    Q, _ = w.instance()
+    ctx = api.da_create(Q, w.dtype_hint if dtype is None else dtype)
+    sch = api.schedule(w.T_hi, w.T_lo, w.schedule, w.n_levels, w.eoff_inc, w.init)
+    gpu = api.da_anneal_ex(ctx, sch, 0, w.replicas, w.steps, w.seed, launch)
+    for r in rows:
+        ref = oracle.anneal(Q, T_hi=w.T_hi, T_lo=w.T_lo, n_levels=w.n_levels,
+                            eoff_inc=w.eoff_inc, init=0 if w.init == "zeros" else 1,
+                            replica_base=r, replicas=1, steps=w.steps, seed=w.seed)
+        for k in KEYS:
+            assert np.array_equal(gpu[k][r], ref[k][0]), (name, r, k)
+    return gpu
+
+
+def test_torus2d_bimodal_1024_sampled(api):
+    """128 replicas x 10^5 steps, int16 storage, the benchmark's launch."""
+    gpu = _sampled(api, "torus2d-bimodal-1024", rows=(0, 127))
+    assert gpu["n_accept"].min() > 0
+
+
+def test_sk_gaussian_1024_sampled(api):
+    """1024 replicas x 10^5 steps of the fixed-point Gaussian SK instance."""
+    _sampled(api, "sk-gaussian-1024", rows=(0, 1023))
+
+
+def test_sk_gaussian_1024_int32_storage(api):
+    """Same workload with couplings forced to int32 storage: identical results."""
+    w = workloads.WORKLOADS["sk-gaussian-1024"]
+    Q, _ = w.instance()
+    sch = api.schedule(w.T_hi, w.T_lo, w.schedule, w.n_levels, w.eoff_inc, w.init)
+    a = api.da_anneal_ex(api.da_create(Q, 0), sch, 0, 64, 20_000, w.seed)
+    b = api.da_anneal_ex(api.da_create(Q, 4), sch, 0, 64, 20_000, w.seed)
+    for k in KEYS:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_sk_bimodal_1024_random_start_sampled(api):
+    """The +-1 variant with a random start (int8 MFMA initial fields)."""
+    w = workloads.WORKLOADS["sk-bimodal-1024-random"]
+    Q, _ = w.instance()
+    ctx = api.da_create(Q)
+    assert ctx.info()["dtype"] == 1
+    sch = api.schedule(w.T_hi, w.T_lo, w.schedule, w.n_levels, w.eoff_inc, w.init)
+    gpu = api.da_anneal_ex(ctx, sch, 0, 1024, 2000, w.seed)
+    ref = oracle.anneal(Q, T_hi=w.T_hi, T_lo=w.T_lo, n_levels=w.n_levels, eoff_inc=w.eoff_inc,
+                        init=1, replica_base=1000, replicas=24, steps=2000, seed=w.seed)
+    for k in KEYS:
+        assert np.array_equal(gpu[k][1000:1024], ref[k]), k
+
+
+def test_argument_errors(api):
+    Q = instances.random_qubo(10, 1)
+    with pytest.raises(api.DaError) as e:
+        api.da_create(np.zeros((0, 0), np.int32))
+    assert e.value.code == api.DA_EINVAL
+    big = np.full((4, 4), 2**29, np.int32)
+    with pytest.raises(api.DaError) as e:
+        api.da_create(big)
+    assert e.value.code == api.DA_ERANGE
+    with pytest.raises(api.DaError) as e:
+        api.da_create(instances.random_qubo(8, 2, lo=-1000, hi=1000), api.DA_DTYPE_I8)
+    assert e.value.code == api.DA_ERANGE
+    ctx = api.da_create(Q)
+    with pytest.raises(api.DaError) as e:
+        api.da_anneal(ctx, api.schedule(1.0, 0.5), 0, 10, 1)
+    assert e.value.code == api.DA_EINVAL
+    with pytest.raises(api.DaError) as e:
+        api.da_anneal(ctx, api.schedule(-1.0, 0.5), 2, 10, 1)
+    assert e.value.code == api.DA_EINVAL
+    with pytest.raises(api.DaError) as e:
+        api.da_pt(ctx, [2.0, 1.0], 1, 1, 1, 0, 1)
+    assert e.value.code == api.DA_EINVAL
+    assert "ok" in api.da_strerror(0)
