@@ -115,14 +115,15 @@ typedef struct da_trace {
  *   flips_per_lane      4, 8 or 16 variables per GPU lane
  *   replicas_per_block  replicas sharing one workgroup (1..16)
  *   w_in_lds            1: stage W in LDS when it fits; -1: never; 0: auto
- *   rng_ahead           1: generate each step's random numbers one step
- *                       ahead, under the row fetch; -1: lazily, only for
- *                       undecided flips; 0: auto */
+ *   rng_waves           1: dedicated random-number waves generate each
+ *                       step's draws one step ahead, off the critical path;
+ *                       -1: the compute waves draw lazily, only for undecided
+ *                       flips; 0: auto */
 typedef struct da_launch {
     int32_t flips_per_lane;
     int32_t replicas_per_block;
     int32_t w_in_lds;
-    int32_t rng_ahead;
+    int32_t rng_waves;
 } da_launch;
 
 /* What the step-kernel launches of a context looked like and how long they
@@ -137,7 +138,7 @@ typedef struct da_kernel_stats {
     int32_t flips_per_lane;
     int32_t replicas_per_block;
     int32_t w_in_lds;
-    int32_t rng_ahead;
+    int32_t rng_waves;         /* random-number waves per replica (0: lazy)  */
     int32_t dtype;             /* bytes per stored coupling                  */
     int32_t reserved;
 } da_kernel_stats;
@@ -260,6 +261,18 @@ const char *da_strerror(int status);
  * the device kernels decide against; exposed for verification. */
 int da_threshold_table(double T, int32_t *thr);
 double da_level_temperature(const da_schedule *schedule, int32_t level);
+
+/* Roofline probe of the row stream (measurement only; allocates its own
+ * matrix).  `chains` workgroups of `waves_per_chain` waves each walk a random
+ * cycle through the rows of an n_rows x row_elems matrix of dtype_bytes (2 or
+ * 4) integers, one dependent row fetch per step -- the access pattern of the
+ * step kernel without its arithmetic.  Reports the time per dependent step
+ * (fetch latency at that working-set size) and the row bytes per second over
+ * all chains.  Errors: DA_EINVAL (sizes; int16 needs n_rows < 32768,
+ * row_elems <= 512 * waves_per_chain), DA_ENOMEM, DA_EDEVICE. */
+int da_probe_row_stream(int32_t n_rows, int32_t row_elems, int32_t dtype_bytes, int32_t chains,
+                        int32_t waves_per_chain, int64_t steps, double *ns_per_step,
+                        double *gbytes_per_s);
 
 /* ---- continuous-batching server ----------------------------------------- */
 typedef struct da_server da_server;

@@ -47,14 +47,14 @@ class da_trace(ctypes.Structure):
 
 class da_launch(ctypes.Structure):
     _fields_ = [("flips_per_lane", _i32), ("replicas_per_block", _i32), ("w_in_lds", _i32),
-                ("rng_ahead", _i32)]
+                ("rng_waves", _i32)]
 
 
 class da_kernel_stats(ctypes.Structure):
     _fields_ = [("kernel_ms", _dbl), ("total_ms", _dbl), ("launches", _i64), ("blocks", _i32),
                 ("threads", _i32),
                 ("flips_per_lane", _i32), ("replicas_per_block", _i32), ("w_in_lds", _i32),
-                ("rng_ahead", _i32), ("dtype", _i32), ("reserved", _i32)]
+                ("rng_waves", _i32), ("dtype", _i32), ("reserved", _i32)]
 
 
 class da_info(ctypes.Structure):
@@ -132,6 +132,8 @@ def lib() -> ctypes.CDLL:
                            ctypes.POINTER(da_job_stats)]),
         "da_job_footprint": (_i64, [_i32, _i32, _i32, _i32]),
         "da_server_destroy": (None, [_P]),
+        "da_probe_row_stream": (_i32, [_i32, _i32, _i32, _i32, _i32, _i64,
+                                       ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -159,8 +161,8 @@ def schedule(T_hi: float, T_lo: float, kind: str | int = "geometric", n_levels: 
 
 
 def launch(flips_per_lane: int = 0, replicas_per_block: int = 0, w_in_lds: int = 0,
-           rng_ahead: int = 0) -> da_launch:
-    return da_launch(int(flips_per_lane), int(replicas_per_block), int(w_in_lds), int(rng_ahead))
+           rng_waves: int = 0) -> da_launch:
+    return da_launch(int(flips_per_lane), int(replicas_per_block), int(w_in_lds), int(rng_waves))
 
 
 class Ctx:
@@ -334,6 +336,16 @@ def da_level_temperature(sched: da_schedule, level: int) -> float:
 
 def da_strerror(code: int) -> str:
     return lib().da_strerror(int(code)).decode()
+
+
+def da_probe_row_stream(n_rows: int, row_elems: int, dtype_bytes: int, chains: int,
+                        waves_per_chain: int, steps: int) -> dict:
+    ns = _dbl()
+    gbs = _dbl()
+    _check(lib().da_probe_row_stream(int(n_rows), int(row_elems), int(dtype_bytes), int(chains),
+                                     int(waves_per_chain), int(steps), ctypes.byref(ns),
+                                     ctypes.byref(gbs)))
+    return {"ns_per_step": ns.value, "GBps": gbs.value}
 
 
 # ---- server -----------------------------------------------------------------

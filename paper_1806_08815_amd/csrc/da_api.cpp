@@ -116,30 +116,43 @@ LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch,
                          bool anneal_mode) {
     LaunchShape sh;
     const int stage = anneal_mode ? 1 : 0;
-    const int ahead = launch ? launch->rng_ahead : 0;
-    // Ahead-of-time draws pay off while the CUs have spare issue slots (few
-    // replicas per CU); lazy draws save ALU work when the chip is full.
-    sh.pre = ahead > 0 ? 1 : (ahead < 0 ? 0 : (R <= 512 ? 1 : 0));
-    sh.F = (launch && launch->flips_per_lane) ? launch->flips_per_lane : 8;
+    int cus = 256;
+    {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    }
+    // Few replicas per CU: each replica's step latency is the limit, so spread
+    // a replica over more waves (4 variables per lane) and move the random
+    // numbers to their own waves.  A full chip is limited by total work: 8
+    // variables per lane and lazy draws.
+    const bool latency_bound = R <= 2 * cus;
+    const int want_help = launch ? launch->rng_waves : 0;
+    bool help = want_help > 0 || (want_help == 0 && latency_bound);
+    sh.F = (launch && launch->flips_per_lane) ? launch->flips_per_lane : (latency_bound ? 4 : 8);
     if (sh.F != 4 && sh.F != 8 && sh.F != 16) sh.F = 8;
     sh.NW = (ctx->N + 64 * sh.F - 1) / (64 * sh.F);
     while (sh.NW > 16) {  // keep a replica within one workgroup
         sh.F *= 2;
         sh.NW = (ctx->N + 64 * sh.F - 1) / (64 * sh.F);
     }
+    const int nblk = (ctx->N + 7) / 8;
+    sh.NH = help ? (nblk + 63) / 64 : 0;
+    if (sh.NW + sh.NH > 16) sh.NH = 0;
+    const int per = sh.NW + sh.NH;
     int rpw = (launch && launch->replicas_per_block) ? launch->replicas_per_block : 1;
-    rpw = std::max(1, std::min(rpw, 16 / sh.NW));
+    rpw = std::max(1, std::min(rpw, 16 / per));
     rpw = std::min(rpw, std::max(R, 1));
     sh.RPW = rpw;
     const int64_t w_bytes = (int64_t)ctx->N * ctx->ld * ctx->dtype;
     const int want = launch ? launch->w_in_lds : 0;
     sh.w_lds = (want >= 0 && w_bytes <= (want > 0 ? device_lds_limit() : 32 * 1024)) ? 1 : 0;
-    sh.threads = 64 * sh.NW * sh.RPW;
+    sh.threads = 64 * per * sh.RPW;
     sh.blocks = (R + sh.RPW - 1) / sh.RPW;
-    sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, sh.w_lds ? (int)w_bytes : 0, stage);
+    sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, sh.w_lds ? (int)w_bytes : 0, stage, sh.NH);
     if (sh.lds > (size_t)device_lds_limit() && sh.w_lds) {
         sh.w_lds = 0;
-        sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0, stage);
+        sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0, stage, sh.NH);
     }
     return sh;
 }
@@ -172,6 +185,7 @@ JobDesc make_job(const da_ctx *ctx, const LevelTables &lt, int32_t R, uint32_t r
     J.round_ptr = nullptr;
     J.K = 0;
     J.NW = sh.NW;
+    J.NH = sh.NH;
     J.RPW = sh.RPW;
     J.w_lds = sh.w_lds;
     J.hdr = lt.d_hdr;
@@ -207,13 +221,13 @@ int device_lds_limit() {
 
 LaunchShape batch_shape(const da_ctx *ctx) {
     LaunchShape sh;
-    sh.pre = 0;
+    sh.NH = 0;
     sh.F = 8;
     sh.NW = (ctx->N + 511) / 512;
     sh.RPW = 16 / sh.NW;
     sh.w_lds = 0;
     sh.threads = 1024;
-    sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0, 1);
+    sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0, 1, 0);
     return sh;
 }
 
@@ -228,7 +242,7 @@ int BatchRunner::prepare(std::string &err) {
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     blocks = cus;
     lds = 0;
-    for (int nw = 1; nw <= 16; ++nw) lds = std::max(lds, run_lds_bytes(nw, 16 / nw, 8, 0, 1));
+    for (int nw = 1; nw <= 16; ++nw) lds = std::max(lds, run_lds_bytes(nw, 16 / nw, 8, 0, 1, 0));
     if (hipMalloc(&d_jobs, sizeof(JobDesc) * kCapJobs) != hipSuccess ||
         hipMalloc(&d_items, sizeof(BatchItem) * kCapItems) != hipSuccess ||
         hipMalloc(&d_n, 4) != hipSuccess || hipMalloc(&d_counter, 4) != hipSuccess ||
@@ -464,7 +478,7 @@ void record_stats(da_ctx *ctx, const LaunchShape &sh, int64_t launches) {
     ctx->last.flips_per_lane = sh.F;
     ctx->last.replicas_per_block = sh.RPW;
     ctx->last.w_in_lds = sh.w_lds;
-    ctx->last.rng_ahead = sh.pre;
+    ctx->last.rng_waves = sh.NH;
     ctx->last.dtype = ctx->dtype;
     ctx->have_stats = true;
 }
@@ -501,7 +515,7 @@ int enqueue_anneal(da_ctx *ctx, const da_schedule *schedule, int64_t replica_bas
             T.E = trace_dev->E;
             T.eoff = trace_dev->eoff;
         }
-        const int e = launch_run(J, sh.F, sh.pre != 0, trace_dev ? &T : nullptr, sh.blocks,
+        const int e = launch_run(J, sh.F, sh.NH > 0, trace_dev ? &T : nullptr, sh.blocks,
                                  sh.threads, sh.lds, s);
         rc = check_hip(ctx, (hipError_t)e, "step kernel launch");
         if (rc) return rc;
@@ -775,7 +789,7 @@ int da_pt(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t r
     auto one_round = [&]() -> int {
         int e = 0;
         if (steps_per_round > 0)
-            e = launch_run(J, sh.F, sh.pre != 0, nullptr, sh.blocks, sh.threads, sh.lds, s);
+            e = launch_run(J, sh.F, sh.NH > 0, nullptr, sh.blocks, sh.threads, sh.lds, s);
         if (!e)
             e = launch_pt_exchange(J.E, ctx->pt_slot2rep, ctx->pt_lvl, ctx->pt_dbeta, ctx->pt_lnU, M,
                                    chains, seed, ctx->pt_round, ctx->pt_swaps, s);

@@ -12,6 +12,8 @@
 //     hdr [L] LevelHdr, brk [...] uint32 acceptance brackets (see below).
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 
 namespace dapt {
@@ -57,7 +59,8 @@ struct JobDesc {
     const int32_t *lvl_of_rep;   // PT mode: level of each replica, else null
     const uint32_t *round_ptr;   // PT mode: device round counter, else null
     int32_t K;                   // PT mode: steps per round
-    int32_t NW;                  // waves per replica
+    int32_t NW;                  // compute waves per replica
+    int32_t NH;                  // random-number waves per replica (0: lazy draws)
     int32_t RPW;                 // replicas per workgroup
     int32_t w_lds;               // W staged in LDS
     const LevelHdr *hdr;
@@ -87,8 +90,8 @@ int launch_rand_bits(uint8_t *X, int32_t R, int32_t N, int32_t ld, uint32_t rid_
 int launch_fields(const JobDesc &J, const uint8_t *X, int32_t R, int32_t *H, void *stream);
 int launch_energy_from_fields(const JobDesc &J, const uint8_t *X, const int32_t *H, int32_t R,
                               int64_t *E_out, bool finish_state, void *stream);
-int launch_run(const JobDesc &J, int F, bool pre, const TraceDesc *trace, int blocks, int threads,
-               size_t lds_bytes, void *stream);
+int launch_run(const JobDesc &J, int F, bool help, const TraceDesc *trace, int blocks,
+               int threads, size_t lds_bytes, void *stream);
 // Persistent batched step kernel; the item count is read from device memory so
 // one captured graph can serve batches of any size.
 int launch_batch(const JobDesc *jobs_dev, const BatchItem *items_dev, const int32_t *n_items_dev,
@@ -106,8 +109,37 @@ int launch_fill_i32(int32_t *dst, int32_t value, int64_t n, void *stream);
 // Dynamic LDS a workgroup may use on the current device (bytes).
 int device_lds_limit();
 
+// LDS of one replica slot of a workgroup (byte offsets): the selection
+// exchange of multi-wave replicas (wave totals, lane records, the energy
+// hand-off) and, with random-number waves, the selection-draw ring and the
+// double-buffered Philox blocks.
+struct SlotLayout {
+    int tot, rec, dEs, vring, draws, bytes;
+};
+__host__ __device__ inline SlotLayout slot_layout(int NW, int NH) {
+    SlotLayout L{0, 0, 0, 0, 0, 0};
+    int off = 0;
+    if (NW > 1 || NH > 0) {
+        L.tot = off;
+        off += 2 * NW * 4;
+        L.rec = off;
+        off += 2 * NW * 64 * 4;
+        L.dEs = off;
+        off += 8;
+    }
+    if (NH > 0) {
+        L.vring = off;
+        off += 16;
+        off = (off + 15) & ~15;
+        L.draws = off;
+        off += 2 * NH * 64 * 16;
+    }
+    L.bytes = (off + 15) & ~15;
+    return L;
+}
+
 // Workgroup LDS bytes the run kernel needs for a launch shape (stage_brk: the
 // level's bracket table is staged in LDS, anneal mode).
-size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk);
+size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk, int NH);
 
 }  // namespace dapt

@@ -89,10 +89,17 @@ __device__ __forceinline__ void wave_prefix(int c, int &excl, int &total) {
     }
 }
 
-// Position of the r-th (0-based) set bit of m.
+// Position of the r-th (0-based) set bit of the F-bit mask m (branch-free).
+template <int F>
 __device__ __forceinline__ int select_bit(uint32_t m, int r) {
-    for (int q = 0; q < r; ++q) m &= m - 1u;
-    return __ffs(m) - 1;
+    int pos = 0, cnt = 0;
+#pragma unroll
+    for (int q = 0; q < F; ++q) {
+        const int b = (m >> q) & 1;
+        pos = (b && cnt == r) ? q : pos;
+        cnt += b;
+    }
+    return pos;
 }
 
 template <int F>
@@ -136,25 +143,26 @@ __device__ __forceinline__ int row16_incl_scan(int v) {
 
 }  // namespace
 
-size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk) {
+size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk, int NH) {
     (void)F;
-    size_t per_slot = 0;
-    if (NW > 1) per_slot = 2 * (size_t)NW * 4 + 2 * (size_t)NW * 64 * 4 + 2 * 4;
+    const SlotLayout SL = slot_layout(NW, NH);
     size_t w = (size_t)((w_lds_bytes + 15) & ~15);
     size_t b = stage_brk ? (size_t)kMaxBuckets * 4 : 0;
-    return w + b + ((per_slot * RPW + 15) & ~(size_t)15);
+    return w + b + (size_t)SL.bytes * RPW;
 }
 
 // Runs steps [s0, s1) for the replicas of one workgroup.  `blk` selects which
 // replicas of the job (rows blk*RPW ..).  All waves of the workgroup execute
 // the same number of loop iterations and barriers.
 //
-// PRE: the random numbers of step s+1 (they depend only on seed, replica,
-// step and variable) are generated right after the row fetch of step s is
-// issued, so Philox runs in the shadow of the memory latency instead of on the
-// step's critical path.  Without PRE they are generated lazily, only for
-// lanes with in-band flips (less ALU work when most flips are decided by the
-// band, e.g. at low temperature).
+// HELP: besides the NW compute waves, each replica has NH random-number
+// waves.  They only run Philox: during step s they write step s+1's 16-bit
+// draws and selection draw into a double-buffered LDS ring, and the per-step
+// barrier hands them over, so the compute waves' critical path (fetch, update,
+// test, select) carries no generator work at all; the generator waves run on
+// issue slots the compute waves leave idle while they wait on memory.
+// Without HELP, draws are generated lazily by the compute waves, only for
+// lanes with in-band flips (least total work when the chip is full).
 // STAGE: one level per workgroup (anneal), its brackets live in LDS; else
 // (parallel tempering) every replica has its own level, read through L1/L2.
 //
@@ -165,21 +173,25 @@ size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk) {
 // buffers (the owning lane writes it after the selection), so it never adds
 // an LDS round trip to the critical path; the energy and the best-state check
 // of step s therefore complete after barrier s+1, before step s+1 flips.
-template <typename WT, int F, bool TRACE, bool PRE, bool STAGE>
+template <typename WT, int F, bool TRACE, bool HELP, bool STAGE>
 __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *smem,
                                           const TraceDesc &T) {
     constexpr int NB = (F + 7) / 8;   // Philox blocks per lane
     typedef typename VecOf<WT, F>::type RowV;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    // wave-level quantities are uniform: keep them in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int NW = J.NW;
-    const int slot = wave / NW;
-    const int wr = wave - slot * NW;
+    const int NH = HELP ? J.NH : 0;
+    const int ncomp = J.RPW * NW;
+    const bool helper = HELP && wave >= ncomp;
+    const int slot = helper ? (wave - ncomp) / NH : wave / NW;
+    const int wr = helper ? (wave - ncomp) - slot * NH : wave - slot * NW;
     const int g = wr * 64 + lane;
     const int i0 = g * F;
     const int rr = blk * J.RPW + slot;
     const bool active = (slot < J.RPW) && (rr < J.R);
-    const bool lane_has = active && (i0 < J.ld);
+    const bool lane_has = !helper && active && (i0 < J.ld);
     const int col0 = lane_has ? i0 : 0;     // row column this lane reads (ghost lanes: 0)
     const uint32_t rid = J.rid_base + (uint32_t)rr;
     const uint32_t k0 = (uint32_t)J.seed;
@@ -187,6 +199,8 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     const int ld = J.ld;
     const int wscale = J.wscale;
     constexpr bool stage = STAGE;
+    const bool sync = HELP || NW > 1;       // a workgroup barrier every step
+    const int nblk = (J.N + 7) >> 3;        // Philox blocks per replica-step
 
     int64_t s0 = J.s0, s1 = J.s1;
     if (J.round_ptr) {
@@ -195,15 +209,17 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         s1 = s0 + J.K;
     }
 
-    // --- LDS carve-up: [W][brackets][selection slots] ------------------------
+    // --- LDS carve-up: [W][brackets][per replica slot] -----------------------
     const int w_bytes = J.w_lds ? ((J.N * ld * (int)sizeof(WT) + 15) & ~15) : 0;
     const WT *Wl = reinterpret_cast<const WT *>(smem);
     uint32_t *brk_l = reinterpret_cast<uint32_t *>(smem + w_bytes);
-    uint8_t *sel = smem + w_bytes + (stage ? kMaxBuckets * 4 : 0);
-    const size_t slot_bytes = (NW > 1) ? (2 * (size_t)NW * 4 + 2 * (size_t)NW * 64 * 4 + 2 * 4) : 0;
-    int *tot = reinterpret_cast<int *>(sel + slot_bytes * slot);        // [2][NW]
-    uint32_t *rec = reinterpret_cast<uint32_t *>(tot + 2 * NW);        // [2][NW*64]
-    int *dEs = reinterpret_cast<int *>(rec + 2 * NW * 64);              // [2]
+    const SlotLayout SL = slot_layout(NW, NH);
+    uint8_t *sel = smem + w_bytes + (stage ? kMaxBuckets * 4 : 0) + (size_t)SL.bytes * slot;
+    int *tot = reinterpret_cast<int *>(sel + SL.tot);              // [2][NW]
+    uint32_t *rec = reinterpret_cast<uint32_t *>(sel + SL.rec);    // [2][NW*64]
+    int *dEs = reinterpret_cast<int *>(sel + SL.dEs);              // [2]
+    uint32_t *vring = reinterpret_cast<uint32_t *>(sel + SL.vring);  // [4] selection draws
+    uint4 *draws = reinterpret_cast<uint4 *>(sel + SL.draws);      // [2][NH*64] Philox blocks
 
     if (J.w_lds) {
         const uint4 *src = reinterpret_cast<const uint4 *>(J.W);
@@ -235,7 +251,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     }
     int64_t E = 0, bE = 0, nacc = 0;
     int32_t eoff = 0;
-    if (active) {
+    if (active && !helper) {
         E = J.E[rr];
         bE = J.bE[rr];
         eoff = J.eoff[rr];
@@ -261,15 +277,37 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     };
     if (stage) stage_brackets();
 
-    uint4 rb[NB];
-    uint32_t vsel = 0;
-    auto gen_draws = [&](int64_t st) {
-#pragma unroll
-        for (int q = 0; q < NB; ++q)
-            rb[q] = philox((uint32_t)(i0 >> 3) + q, (uint32_t)st, rid, kTagMetropolis, k0, k1);
-        vsel = philox(0u, (uint32_t)st, rid, kTagSelect, k0, k1).x;
+    // generator waves: the draws of step st into ring slot st & 1
+    auto produce = [&](int64_t st) {
+        const int b = g;   // Philox block of this generator lane
+        if (active && b < nblk)
+            draws[(int)(st & 1) * NH * 64 + b] =
+                philox((uint32_t)b, (uint32_t)st, rid, kTagMetropolis, k0, k1);
+        if (active && wr == NH - 1) {
+            const uint32_t v = philox(0u, (uint32_t)st, rid, kTagSelect, k0, k1).x;
+            if (lane == 0) vring[(int)(st & 3)] = v;
+        }
     };
-    if (PRE) gen_draws(s0);
+    // compute waves: this lane's draws of step st (written by the generators)
+    auto consume = [&](int64_t st, uint4 (&dst)[NB]) {
+        // lanes past the last variable only hold ghost flips: clamp their reads
+        const uint4 *src = draws + (int)(st & 1) * NH * 64;
+        if (F >= 8) {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) dst[q] = src[min((i0 >> 3) + q, NH * 64 - 1)];
+        } else {
+            const uint2 *s2 = reinterpret_cast<const uint2 *>(src);
+            const uint2 p = s2[min(i0 >> 2, 2 * NH * 64 - 1)];   // half of block i0 >> 3
+            dst[0] = make_uint4(p.x, p.y, p.x, p.y);
+        }
+    };
+
+    uint4 rb[NB];
+    if (HELP) {
+        if (helper) produce(s0);
+        __syncthreads();
+        if (!helper) consume(s0, rb);
+    }
 
     bool pend = false;   // NW > 1: the previous step's energy change is in dEs
     for (int64_t s = s0; s < s1; ++s) {
@@ -280,69 +318,99 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             if (stage) stage_brackets();
         }
         const int par = (int)(s & 1);
-
-        // 1. cost of every flip and the draw-free decisions
         int d[F];
-        uint32_t acc = 0, inb = 0;
-#pragma unroll
-        for (int f = 0; f < F; ++f) {
-            const int dd = (((xb >> f) & 1u) ? -h[f] : h[f]) - eoff;
-            d[f] = dd;
-            const bool v = (vmask >> f) & 1u;
-            if (v && dd <= hd.tmin) acc |= 1u << f;
-            else if (v && dd <= hd.tmax) inb |= 1u << f;
-        }
+        uint32_t acc = 0;
+        int c = 0, excl = 0, wtot = 0;
 
-        // 2. in-band flips: 16-bit draw and bracket.  All bracket reads are
-        // issued together (out-of-band flips read entry 0) and waited on once;
-        // the threshold table itself is read only inside a non-exact bracket.
-        if (inb) {
-            if (!PRE) {
-#pragma unroll
-                for (int q = 0; q < NB; ++q)
-                    rb[q] = philox((uint32_t)(i0 >> 3) + q, (uint32_t)s, rid, kTagMetropolis, k0, k1);
-            }
-            uint32_t u[F], e[F];
+        if (helper) {
+            if (s + 1 < s1) produce(s + 1);
+        } else {
+            // 1. cost of every flip and the draw-free decisions (branch-free)
+            uint32_t inb = 0;
 #pragma unroll
             for (int f = 0; f < F; ++f) {
-                const int slice = (F >= 8) ? (f & 7) : ((i0 & 7) + f);
-                const uint32_t wv = word_of(rb[f >> 3], slice >> 1);
-                u[f] = (slice & 1) ? (wv >> 16) : (wv & 0xFFFFu);
-                const int bi = ((inb >> f) & 1u) ? ((d[f] - hd.tmin - 1) >> hd.sh) : 0;
-                e[f] = stage ? brk_l[bi] : J.brk[hd.off + bi];
+                const int hv = h[f];
+                const int dd = (((xb >> f) & 1u) ? -hv : hv) - eoff;
+                d[f] = dd;
+                const uint32_t v = (vmask >> f) & 1u;
+                acc |= (v & (uint32_t)(dd <= hd.tmin)) << f;
+                inb |= (v & (uint32_t)(dd > hd.tmin) & (uint32_t)(dd <= hd.tmax)) << f;
             }
-            uint32_t fine = 0;
+            // 2. in-band flips: 16-bit draw and bracket.  Every bracket read is
+            // issued (out-of-band flips read entry 0) and waited on once; the
+            // threshold table is read only inside a non-exact bracket (rare).
+            if (inb) {
+                if (!HELP) {
 #pragma unroll
-            for (int f = 0; f < F; ++f) {
-                if (!((inb >> f) & 1u)) continue;
-                const uint32_t lo = e[f] & 0xFFFFu, hi = e[f] >> 16;
-                if (u[f] < lo) acc |= 1u << f;
-                else if (u[f] < hi) fine |= 1u << f;
+                    for (int q = 0; q < NB; ++q)
+                        rb[q] = philox((uint32_t)(i0 >> 3) + q, (uint32_t)s, rid, kTagMetropolis,
+                                       k0, k1);
+                }
+                uint32_t u[F], e[F];
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    const int slice = (F >= 8) ? (f & 7) : ((HELP ? 0 : (i0 & 7)) + f);
+                    const uint32_t wv = word_of(rb[f >> 3], slice >> 1);
+                    u[f] = (slice & 1) ? (wv >> 16) : (wv & 0xFFFFu);
+                    const int bi = ((inb >> f) & 1u) ? ((d[f] - hd.tmin - 1) >> hd.sh) : 0;
+                    e[f] = stage ? brk_l[bi] : J.brk[hd.off + bi];
+                }
+                uint32_t fine = 0;
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    const uint32_t ib = (inb >> f) & 1u;
+                    const uint32_t lo = e[f] & 0xFFFFu, hi = e[f] >> 16;
+                    acc |= (ib & (uint32_t)(u[f] < lo)) << f;
+                    fine |= (ib & (uint32_t)(u[f] >= lo) & (uint32_t)(u[f] < hi)) << f;
+                }
+                if (fine) {
+                    const int32_t *thr = J.thr + (size_t)lvl * 65536;
+                    int t[F];
+#pragma unroll
+                    for (int f = 0; f < F; ++f) t[f] = thr[((fine >> f) & 1u) ? u[f] : 0u];
+#pragma unroll
+                    for (int f = 0; f < F; ++f)
+                        acc |= (((fine >> f) & 1u) & (uint32_t)(d[f] <= t[f])) << f;
+                }
             }
-            if (fine) {
-                const int32_t *thr = J.thr + (size_t)lvl * 65536;
-#pragma unroll
-                for (int f = 0; f < F; ++f)
-                    if (((fine >> f) & 1u) && d[f] <= thr[u[f]]) acc |= 1u << f;
+            // 3a. accepted count, prefix over the wave; publish for the others
+            c = __popc(acc);
+            wave_prefix<CountBits<F>::value>(c, excl, wtot);
+            if (NW > 1) {
+                rec[par * NW * 64 + g] = acc | (xb << 16);
+                if (lane == 0) tot[par * NW + wr] = wtot;
             }
         }
+        if (sync) __syncthreads();
+        if (helper) continue;
 
-        // 3. accepted count and the chosen flip
-        const int c = __popc(acc);
-        int excl, wtot;
-        wave_prefix<CountBits<F>::value>(c, excl, wtot);
-
-        int m, k = 0, xk = 0, dk = 0, ts = 0, bit = 0, ws = 0;
+        // 3b. the chosen flip.  Everything this step needs from LDS is read
+        // in one straight-line group (clamped indices, no branches), so the
+        // wave waits for LDS once.
+        uint4 rbn[NB];
+        if (HELP) consume(s + 1 < s1 ? s + 1 : s, rbn);
+        const uint32_t vs = HELP ? vring[(int)(s & 3)] : 0u;
+        int dEp = 0, tw = 0;
+        uint32_t r4[4] = {0u, 0u, 0u, 0u};
+        if (NW > 1) {
+            dEp = dEs[par ^ 1];
+            const int twr = tot[par * NW + min(lane, NW - 1)];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) r4[q] = rec[par * NW * 64 + min(q, NW - 1) * 64 + lane];
+            tw = lane < NW ? twr : 0;
+        }
+        int m, k = 0, xk = 0, dk = 0, bit = 0;
         if (NW == 1) {
             m = wtot;
             if (m > 0) {
-                const uint32_t v = PRE ? vsel : philox(0u, (uint32_t)s, rid, kTagSelect, k0, k1).x;
+                const uint32_t v = HELP ? (uint32_t)__builtin_amdgcn_readfirstlane((int)vs)
+                                        : philox(0u, (uint32_t)s, rid, kTagSelect, k0, k1).x;
                 const int j = (int)(((uint64_t)v * (uint32_t)m) >> 32);
                 const uint64_t bal = ballot(excl + c > j);
-                ts = __ffsll((unsigned long long)bal) - 1;
+                const int ts = __ffsll((unsigned long long)bal) - 1;
                 const int rloc = j - readlane(excl, ts);
                 const uint32_t msk = (uint32_t)readlane((int)acc, ts);
-                bit = select_bit(msk, rloc);
+                bit = select_bit<F>(msk, rloc);
                 k = ts * F + bit;
                 xk = (readlane((int)xb, ts) >> bit) & 1;
                 int dsel = d[0];
@@ -351,33 +419,23 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 dk = readlane(dsel, ts);
             }
         } else {
-            // publish this wave's lanes, then one barrier
-            rec[par * NW * 64 + g] = acc | (xb << 16);
-            if (lane == 0) tot[par * NW + wr] = wtot;
-            __syncthreads();
             // the previous step's energy change (written by its owner lane)
             if (pend) {
-                E += (int64_t)dEs[par ^ 1];
-                if (E < bE) {
-                    bE = E;
-                    bxb = xb;
-                }
+                E += (int64_t)__builtin_amdgcn_readfirstlane(dEp);
+                const bool better = E < bE;
+                bE = better ? E : bE;
+                bxb = better ? xb : bxb;
                 if (TRACE && active && g == 0) T.E[rr * T.stride + (s - 1 - s0)] = E;
                 pend = false;
-            }
-            const int tw = (lane < NW) ? tot[par * NW + lane] : 0;
-            uint32_t r4[4];
-            if (NW <= 4) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) r4[q] = (q < NW) ? rec[par * NW * 64 + q * 64 + lane] : 0u;
             }
             const int scan = row16_incl_scan(tw);
             m = readlane(scan, NW - 1);
             if (m > 0) {
-                const uint32_t v = PRE ? vsel : philox(0u, (uint32_t)s, rid, kTagSelect, k0, k1).x;
+                const uint32_t v = HELP ? (uint32_t)__builtin_amdgcn_readfirstlane((int)vs)
+                                        : philox(0u, (uint32_t)s, rid, kTagSelect, k0, k1).x;
                 const int j = (int)(((uint64_t)v * (uint32_t)m) >> 32);
                 const uint64_t wbal = ballot(lane < NW && scan > j);
-                ws = __ffsll((unsigned long long)wbal) - 1;
+                const int ws = __ffsll((unsigned long long)wbal) - 1;
                 const int jw = j - (readlane(scan, ws) - readlane(tw, ws));
                 uint32_t r2;
                 if (NW <= 4) {
@@ -391,34 +449,31 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 int excl2, tot2;
                 wave_prefix<CountBits<F>::value>(c2, excl2, tot2);
                 const uint64_t bal = ballot(excl2 + c2 > jw);
-                ts = __ffsll((unsigned long long)bal) - 1;
+                const int ts = __ffsll((unsigned long long)bal) - 1;
                 const int rloc = jw - readlane(excl2, ts);
                 const uint32_t rs = (uint32_t)readlane((int)r2, ts);
-                bit = select_bit(rs & 0xFFFFu, rloc);
+                bit = select_bit<F>(rs & 0xFFFFu, rloc);
                 k = (ws * 64 + ts) * F + bit;
                 xk = (rs >> (16 + bit)) & 1;
             }
         }
 
         if (m > 0) {
-            // 4. fetch row k of W (the step's only bulk traffic) ...
+            // 4. fetch row k of W (the step's only bulk traffic) and apply the
+            // flip: state, energy, every field
             RowV raw;
             if (J.w_lds) raw = *reinterpret_cast<const RowV *>(Wl + (size_t)k * ld + col0);
             else raw = *reinterpret_cast<const RowV *>(reinterpret_cast<const WT *>(J.W) +
                                                         (size_t)k * ld + col0);
-            // ... and, while it is in flight, the next step's random numbers
-            if (PRE && s + 1 < s1) gen_draws(s + 1);
-            // 5. apply the flip: state, energy, every field from row k
             const int delta = xk ? -1 : 1;
-            if (g == (k / F)) {
-                if (NW > 1) {
-                    int dsel = d[0];
+            const bool owner = g == (k / F);
+            if (NW > 1 && owner) {
+                int dsel = d[0];
 #pragma unroll
-                    for (int f = 1; f < F; ++f) dsel = (bit == f) ? d[f] : dsel;
-                    dEs[par] = dsel + eoff;
-                }
-                xb ^= 1u << (k % F);
+                for (int f = 1; f < F; ++f) dsel = (bit == f) ? d[f] : dsel;
+                dEs[par] = dsel + eoff;
             }
+            xb ^= owner ? (1u << (k % F)) : 0u;
             if (wscale == 1) {
 #pragma unroll
                 for (int f = 0; f < F; ++f) h[f] += delta > 0 ? (int)raw[f] : -(int)raw[f];
@@ -429,18 +484,20 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             ++nacc;
             if (NW == 1) {
                 E += (int64_t)dk + eoff;
-                if (E < bE) {
-                    bE = E;
-                    bxb = xb;
-                }
+                const bool better = E < bE;
+                bE = better ? E : bE;
+                bxb = better ? xb : bxb;
             } else {
                 pend = true;
             }
             eoff = 0;
         } else {
-            if (PRE && s + 1 < s1) gen_draws(s + 1);
             eoff = min(eoff + J.eoff_inc, kEoffMax);
             k = -1;
+        }
+        if (HELP) {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) rb[q] = rbn[q];
         }
         if (TRACE && active && g == 0) {
             T.k[rr * T.stride + (s - s0)] = k;
@@ -448,7 +505,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             if (NW == 1 || k < 0) T.E[rr * T.stride + (s - s0)] = E;
         }
     }
-    if (NW > 1) {
+    if (NW > 1 || HELP) {
         // the last step's energy change
         __syncthreads();
         if (pend) {
@@ -460,6 +517,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             if (TRACE && active && g == 0) T.E[rr * T.stride + (s1 - 1 - s0)] = E;
         }
     }
+    if (helper) return;
 
     // --- state back to HBM -------------------------------------------------
     if (lane_has) {
@@ -486,10 +544,10 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     }
 }
 
-template <typename WT, int F, bool TRACE, bool PRE, bool STAGE>
+template <typename WT, int F, bool TRACE, bool HELP, bool STAGE>
 __global__ __launch_bounds__(1024) void k_run(JobDesc J, TraceDesc T) {
     extern __shared__ __align__(16) uint8_t smem[];
-    run_block<WT, F, TRACE, PRE, STAGE>(J, blockIdx.x, smem, T);
+    run_block<WT, F, TRACE, HELP, STAGE>(J, blockIdx.x, smem, T);
 }
 
 // Persistent batched form: workgroups pull (job, replica-block) items from a
@@ -730,48 +788,48 @@ inline int grid_for(int64_t n, int threads) {
     return (int)g;
 }
 
-template <typename WT, int F, bool TRACE, bool PRE>
+template <typename WT, int F, bool TRACE, bool HELP>
 int launch_run_t(const JobDesc &J, const TraceDesc &T, int blocks, int threads, size_t lds,
                  void *stream) {
     if (J.lvl_of_rep)
-        hipLaunchKernelGGL((k_run<WT, F, TRACE, PRE, false>), dim3(blocks), dim3(threads), lds,
+        hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, false>), dim3(blocks), dim3(threads), lds,
                            S(stream), J, T);
     else
-        hipLaunchKernelGGL((k_run<WT, F, TRACE, PRE, true>), dim3(blocks), dim3(threads), lds,
+        hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true>), dim3(blocks), dim3(threads), lds,
                            S(stream), J, T);
     return (int)hipGetLastError();
 }
 
-template <typename WT, bool TRACE, bool PRE>
+template <typename WT, bool TRACE, bool HELP>
 int launch_run_f(const JobDesc &J, int F, const TraceDesc &T, int blocks, int threads, size_t lds,
                  void *stream) {
     switch (F) {
-        case 4: return launch_run_t<WT, 4, TRACE, PRE>(J, T, blocks, threads, lds, stream);
-        case 8: return launch_run_t<WT, 8, TRACE, PRE>(J, T, blocks, threads, lds, stream);
-        case 16: return launch_run_t<WT, 16, TRACE, PRE>(J, T, blocks, threads, lds, stream);
+        case 4: return launch_run_t<WT, 4, TRACE, HELP>(J, T, blocks, threads, lds, stream);
+        case 8: return launch_run_t<WT, 8, TRACE, HELP>(J, T, blocks, threads, lds, stream);
+        case 16: return launch_run_t<WT, 16, TRACE, HELP>(J, T, blocks, threads, lds, stream);
         default: return (int)hipErrorInvalidValue;
     }
 }
 
 template <typename WT>
-int launch_run_w(const JobDesc &J, int F, bool pre, const TraceDesc *trace, int blocks,
+int launch_run_w(const JobDesc &J, int F, bool help, const TraceDesc *trace, int blocks,
                  int threads, size_t lds, void *stream) {
     const TraceDesc none{nullptr, nullptr, nullptr, 0};
     if (trace) {
-        return pre ? launch_run_f<WT, true, true>(J, F, *trace, blocks, threads, lds, stream)
-                   : launch_run_f<WT, true, false>(J, F, *trace, blocks, threads, lds, stream);
+        return help ? launch_run_f<WT, true, true>(J, F, *trace, blocks, threads, lds, stream)
+                    : launch_run_f<WT, true, false>(J, F, *trace, blocks, threads, lds, stream);
     }
-    return pre ? launch_run_f<WT, false, true>(J, F, none, blocks, threads, lds, stream)
-               : launch_run_f<WT, false, false>(J, F, none, blocks, threads, lds, stream);
+    return help ? launch_run_f<WT, false, true>(J, F, none, blocks, threads, lds, stream)
+                : launch_run_f<WT, false, false>(J, F, none, blocks, threads, lds, stream);
 }
 }  // namespace
 
-int launch_run(const JobDesc &J, int F, bool pre, const TraceDesc *trace, int blocks, int threads,
-               size_t lds_bytes, void *stream) {
+int launch_run(const JobDesc &J, int F, bool help, const TraceDesc *trace, int blocks,
+               int threads, size_t lds_bytes, void *stream) {
     switch (J.dtype) {
-        case 1: return launch_run_w<int8_t>(J, F, pre, trace, blocks, threads, lds_bytes, stream);
-        case 2: return launch_run_w<int16_t>(J, F, pre, trace, blocks, threads, lds_bytes, stream);
-        case 4: return launch_run_w<int32_t>(J, F, pre, trace, blocks, threads, lds_bytes, stream);
+        case 1: return launch_run_w<int8_t>(J, F, help, trace, blocks, threads, lds_bytes, stream);
+        case 2: return launch_run_w<int16_t>(J, F, help, trace, blocks, threads, lds_bytes, stream);
+        case 4: return launch_run_w<int32_t>(J, F, help, trace, blocks, threads, lds_bytes, stream);
         default: return (int)hipErrorInvalidValue;
     }
 }

@@ -1,0 +1,124 @@
+// da_probe.hip -- memory roofline of the DA row stream.
+//
+// Each step of the annealer fetches one row of the coupling matrix, chosen by
+// the previous step's selection, so a replica has exactly one dependent row
+// fetch in flight.  This probe reproduces that access pattern without the
+// rest of the step: `chains` independent chains (one workgroup of `waves`
+// waves each, like a replica) walk a random permutation of the rows of an
+// n_rows x row_elems matrix; every wave loads its share of the current row
+// with the same vector loads as the step kernel, and the next row index is
+// read out of the loaded data, so fetches are serialised per chain.  The time
+// per step is the dependent-fetch latency at that working-set size (L2, MALL
+// or HBM); rows * chains / time is the achievable row-stream bandwidth for a
+// given number of chains in flight.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "da.h"
+
+namespace {
+
+template <typename WT>
+__global__ __launch_bounds__(1024) void k_row_chase(const WT *__restrict__ M, int32_t ld,
+                                                    int32_t n_rows, int64_t steps, int32_t *sink) {
+    constexpr int F = 8;
+    typedef WT V __attribute__((ext_vector_type(F)));
+    __shared__ int next;
+    const int lane = threadIdx.x & 63;
+    const int g = threadIdx.x;
+    int k = (int)((blockIdx.x * 2654435761u) % (uint32_t)n_rows);
+    int acc = 0;
+    const int col = (g * F < ld) ? g * F : 0;
+    for (int64_t s = 0; s < steps; ++s) {
+        const V v = *reinterpret_cast<const V *>(M + (size_t)k * ld + col);
+        int part = 0;
+#pragma unroll
+        for (int f = 0; f < F; ++f) part += (int)v[f];
+        acc += part;
+        // row index of the next step, from the first element of this row
+        if (blockDim.x > 64) {
+            if (g == 0) next = (int)v[0];
+            __syncthreads();
+            k = next;
+            __syncthreads();
+        } else {
+            k = __builtin_amdgcn_readfirstlane((int)v[0]);
+        }
+        k = (k & 0x7fffffff) % n_rows;
+    }
+    if (lane == 0) sink[blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)] = acc;
+}
+
+template <typename WT>
+int run_probe(int32_t n_rows, int32_t row_elems, int32_t chains, int32_t waves, int64_t steps,
+              double *ns_per_step, double *gbytes_per_s) {
+    const int32_t ld = (row_elems + 511) / 512 * 512;
+    if (waves * 64 * 8 < row_elems) return DA_EINVAL;
+    // random permutation cycle: element 0 of row r names the next row
+    std::vector<WT> host((size_t)n_rows * ld, (WT)1);
+    std::vector<int32_t> perm((size_t)n_rows);
+    for (int32_t r = 0; r < n_rows; ++r) perm[(size_t)r] = r;
+    uint64_t x = 0x9E3779B97F4A7C15ull;
+    for (int32_t r = n_rows - 1; r > 0; --r) {
+        x ^= x << 13; x ^= x >> 7; x ^= x << 17;
+        const int32_t j = (int32_t)(x % (uint64_t)(r + 1));
+        std::swap(perm[(size_t)r], perm[(size_t)j]);
+    }
+    for (int32_t q = 0; q < n_rows; ++q)
+        host[(size_t)perm[(size_t)q] * ld] = (WT)perm[(size_t)((q + 1) % n_rows)];
+    WT *dM = nullptr;
+    int32_t *sink = nullptr;
+    if (hipMalloc(&dM, host.size() * sizeof(WT)) != hipSuccess) return DA_ENOMEM;
+    if (hipMalloc(&sink, (size_t)chains * waves * 4) != hipSuccess) {
+        (void)hipFree(dM);
+        return DA_ENOMEM;
+    }
+    int rc = DA_OK;
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    if (hipMemcpy(dM, host.data(), host.size() * sizeof(WT), hipMemcpyHostToDevice) != hipSuccess)
+        rc = DA_EDEVICE;
+    if (!rc) {
+        // warm caches with a short run, then time
+        hipLaunchKernelGGL(k_row_chase<WT>, dim3(chains), dim3(64 * waves), 0, 0, dM, ld, n_rows,
+                           (int64_t)(steps / 10 + 1), sink);
+        (void)hipEventRecord(a, 0);
+        hipLaunchKernelGGL(k_row_chase<WT>, dim3(chains), dim3(64 * waves), 0, 0, dM, ld, n_rows,
+                           steps, sink);
+        (void)hipEventRecord(b, 0);
+        if (hipEventSynchronize(b) != hipSuccess) rc = DA_EDEVICE;
+    }
+    if (!rc) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        const double t = ms * 1e-3;
+        *ns_per_step = t / (double)steps * 1e9;
+        *gbytes_per_s = (double)row_elems * sizeof(WT) * chains * (double)steps / t / 1e9;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipFree(dM);
+    (void)hipFree(sink);
+    return rc;
+}
+
+}  // namespace
+
+extern "C" int da_probe_row_stream(int32_t n_rows, int32_t row_elems, int32_t dtype_bytes,
+                                   int32_t chains, int32_t waves_per_chain, int64_t steps,
+                                   double *ns_per_step, double *gbytes_per_s) {
+    if (n_rows < 2 || row_elems < 8 || chains < 1 || waves_per_chain < 1 ||
+        waves_per_chain > 16 || steps < 1 || !ns_per_step || !gbytes_per_s)
+        return DA_EINVAL;
+    if (dtype_bytes == 2 && n_rows > 32767) return DA_EINVAL;
+    switch (dtype_bytes) {
+        case 2: return run_probe<int16_t>(n_rows, row_elems, chains, waves_per_chain, steps,
+                                          ns_per_step, gbytes_per_s);
+        case 4: return run_probe<int32_t>(n_rows, row_elems, chains, waves_per_chain, steps,
+                                          ns_per_step, gbytes_per_s);
+        default: return DA_EINVAL;
+    }
+}

@@ -59,9 +59,9 @@ struct StateBuf {
 
 // Launch shape of the step kernel.
 struct LaunchShape {
-    int pre = 1;        // random numbers one step ahead
     int F = 8;
-    int NW = 1;
+    int NW = 1;         // compute waves per replica
+    int NH = 0;         // random-number waves per replica (0: lazy draws)
     int RPW = 1;
     int w_lds = 0;
     int threads = 64;

@@ -62,13 +62,15 @@ def test_energy(api, kind, N, dtype):
     assert E.tolist() == want
 
 
+@pytest.mark.parametrize("rng", [1, -1])
 @pytest.mark.parametrize("kind,N,dtype,F,rpw", [
     ("sk", 20, 0, 8, 1), ("sk", 64, 0, 8, 1), ("sk", 64, 2, 4, 2), ("sk", 100, 4, 16, 3),
     ("random", 70, 0, 8, 2), ("random", 257, 2, 8, 1), ("gauss", 300, 0, 4, 1),
     ("sk", 513, 0, 8, 1), ("sk", 1000, 2, 8, 2), ("gauss", 1024, 4, 16, 1),
-    ("random_big", 600, 4, 4, 1), ("sk", 1536, 1, 8, 1),
+    ("random_big", 600, 4, 4, 1), ("sk", 1536, 1, 8, 1), ("sk", 1024, 2, 4, 1),
+    ("gauss", 2048, 0, 4, 1),
 ])
-def test_trace_parity(api, kind, N, dtype, F, rpw):
+def test_trace_parity(api, kind, N, dtype, F, rpw, rng):
     Q = _q(kind, N, 5)
     if kind == "gauss":
         T_hi, T_lo, inc = 3.0 * 2**16, 0.05 * 2**16, 2**16
@@ -79,7 +81,7 @@ def test_trace_parity(api, kind, N, dtype, F, rpw):
     R, S, L = 5, 700, 16
     ctx = api.da_create(Q, dtype)
     sch = api.schedule(T_hi, T_lo, "geometric", L, eoff_inc=inc)
-    gpu = api.da_anneal_ex(ctx, sch, 3, R, S, 11, api.launch(F, rpw, 0), trace=True)
+    gpu = api.da_anneal_ex(ctx, sch, 3, R, S, 11, api.launch(F, rpw, 0, rng), trace=True)
     ref = oracle.anneal(Q, T_hi=T_hi, T_lo=T_lo, n_levels=L, eoff_inc=inc, replica_base=3,
                         replicas=R, steps=S, seed=11, trace=True)
     _same(gpu, ref, ("trace_k", "trace_E", "trace_eoff") + KEYS)
@@ -148,8 +150,8 @@ def test_replica_base_replay(api):
     Q = _q("sk", 300, 4)
     ctx = api.da_create(Q)
     sch = api.schedule(20.0, 0.5, eoff_inc=1)
-    batch = api.da_anneal_ex(ctx, sch, 0, 24, 2000, 3, api.launch(8, 4, 0))
+    batch = api.da_anneal_ex(ctx, sch, 0, 24, 2000, 3, api.launch(8, 4, 0, -1))
     for r in (0, 13, 23):
-        one = api.da_anneal_ex(ctx, sch, r, 1, 2000, 3, api.launch(16, 1, 0))
+        one = api.da_anneal_ex(ctx, sch, r, 1, 2000, 3, api.launch(16, 1, 0, 1))
         for k in KEYS:
             assert np.array_equal(one[k][0], batch[k][r])
