@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -382,6 +383,99 @@ int derive_storage(const int32_t *Q, int32_t N, int32_t dtype_hint, int32_t &dty
     return DA_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner.  Launch shapes never change results, only speed, so the first
+// anneal of each (device, N, coupling type, replica-count bucket) times every
+// candidate shape on a window of its own schedule, run on scratch state, and
+// keeps the fastest for later calls.  DAPT_AUTOTUNE=0 disables it.
+// ---------------------------------------------------------------------------
+namespace {
+struct TuneKey {
+    int dev, N, dtype, rbucket;
+    bool operator<(const TuneKey &o) const {
+        if (dev != o.dev) return dev < o.dev;
+        if (N != o.N) return N < o.N;
+        if (dtype != o.dtype) return dtype < o.dtype;
+        return rbucket < o.rbucket;
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, da_launch> g_tune;
+
+bool tune_enabled() {
+    const char *e = std::getenv("DAPT_AUTOTUNE");
+    return !(e && e[0] == '0');
+}
+}  // namespace
+
+LaunchShape tuned_shape(da_ctx *ctx, const LevelTables &lt, int32_t R, int64_t steps,
+                        const da_schedule &sched, hipStream_t s) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    int rb = 1;
+    while (rb < R) rb <<= 1;
+    const TuneKey key{dev, ctx->N, ctx->dtype, rb};
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) return choose_shape(ctx, R, &it->second, true);
+    }
+    const int64_t window = std::min<int64_t>(steps, 384);
+    if (window < 64) return choose_shape(ctx, R, nullptr, true);
+    StateBuf scratch;
+    std::string err;
+    if (!scratch.ensure(R, ctx->ld, err)) return choose_shape(ctx, R, nullptr, true);
+    hipEvent_t a = nullptr, b = nullptr;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    da_launch best{0, 0, 0, 0};
+    float best_ms = 1e30f;
+    for (int F : {4, 8}) {
+        for (int rpw : {1, 2, 4}) {
+            for (int rng : {1, -1}) {
+                const da_launch cand{F, rpw, 0, rng};
+                const LaunchShape sh = choose_shape(ctx, R, &cand, true);
+                if (sh.RPW != rpw || sh.F != F || sh.threads > 1024 ||
+                    sh.lds > (size_t)device_lds_limit())
+                    continue;
+                JobDesc J = make_job(ctx, lt, R, 0u, 1u, steps, sched, sh);
+                J.h = scratch.h;
+                J.x = scratch.x;
+                J.bx = scratch.bx;
+                J.E = scratch.E;
+                J.bE = scratch.bE;
+                J.eoff = scratch.eoff;
+                J.nacc = scratch.nacc;
+                J.s0 = steps / 3;
+                J.s1 = J.s0 + window;
+                if (launch_state_zero(J, s) != 0) continue;
+                (void)hipEventRecord(a, s);
+                const int e = launch_run(J, sh.F, sh.NH > 0, nullptr, sh.blocks, sh.threads, sh.lds, s);
+                (void)hipEventRecord(b, s);
+                if (e != 0 || hipEventSynchronize(b) != hipSuccess) {
+                    (void)hipGetLastError();
+                    continue;
+                }
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, a, b);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = cand;
+                }
+            }
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    scratch.release();
+    if (best.flips_per_lane == 0) return choose_shape(ctx, R, nullptr, true);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune[key] = best;
+    }
+    return choose_shape(ctx, R, &best, true);
+}
+
 int next_events(da_ctx *ctx, hipEvent_t &e0, hipEvent_t &e1) {
     if (ctx->ev_used == kEventPool) {
         // fold the window into running totals so the pool stays bounded
@@ -499,7 +593,9 @@ int enqueue_anneal(da_ctx *ctx, const da_schedule *schedule, int64_t replica_bas
     if (!lt) return fail(ctx, DA_ENOMEM, err);
     ctx->keep_tables = lt;
     if (!ctx->st.ensure(replicas, ctx->ld, err)) return fail(ctx, DA_ENOMEM, err);
-    const LaunchShape sh = choose_shape(ctx, replicas, launch, true);
+    const LaunchShape sh = (launch == nullptr && trace_dev == nullptr && tune_enabled())
+                               ? tuned_shape(ctx, *lt, replicas, steps, *schedule, s)
+                               : choose_shape(ctx, replicas, launch, true);
     J = make_job(ctx, *lt, replicas, (uint32_t)replica_base, seed, steps, *schedule, sh);
     rc = init_state(ctx, J, schedule->init, s);
     if (rc) return rc;

@@ -145,6 +145,10 @@ int check_hip(da_ctx *ctx, hipError_t e, const char *what);
 int validate_schedule(const da_schedule *s, std::string &err);
 LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch,
                          bool anneal_mode);
+// Fastest measured shape for this instance size, coupling type and replica
+// count (timed once on scratch state, then cached).
+LaunchShape tuned_shape(da_ctx *ctx, const LevelTables &lt, int32_t R, int64_t steps,
+                        const da_schedule &sched, hipStream_t s);
 JobDesc make_job(const da_ctx *ctx, const LevelTables &lt, int32_t R, uint32_t rid_base,
                  uint64_t seed, int64_t steps, const da_schedule &s, const LaunchShape &sh);
 int init_state(da_ctx *ctx, const JobDesc &J, int init, hipStream_t stream);
