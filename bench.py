@@ -54,6 +54,73 @@ def describe(w):
             f"E_off increment {w.eoff_inc}, {w.init} start, Philox seed {w.seed}")
 
 
+def serve_bench(api, workloads, n_jobs: int, seed: int, budget_gb: float, epoch_steps: int,
+                steps_range=(10_000, 50_000)):
+    """Served stream (continuous batching) against plain one-job-per-launch
+    service of the same jobs in arrival order.  Latency = completion - arrival."""
+    import numpy as np
+    import torch
+
+    jobs = workloads.serve_stream(n_jobs, seed, rate_hz=1.0, steps_range=steps_range)
+    Qs = [workloads.make_instance(j["kind"], j["N"], j["instance_seed"])[0] for j in jobs]
+    scheds = [api.schedule(j["T_hi"], j["T_lo"], "geometric", 128, j["eoff_inc"]) for j in jobs]
+    work = sum(j["replicas"] * j["steps"] * j["N"] for j in jobs)
+
+    # plain service: each job alone through da_anneal (one launch), FIFO
+    service = []
+    for j, Q, sch in zip(jobs, Qs, scheds):
+        ctx = api.da_create(Q)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        api.da_anneal(ctx, sch, j["replicas"], j["steps"], j["seed"])
+        service.append(time.perf_counter() - t)
+        ctx.close()
+    busy = sum(service)
+
+    def run_stream(arrivals):
+        srv = api.da_server_create(int(budget_gb * 2**30), epoch_steps=epoch_steps)
+        t0 = time.perf_counter()
+        tickets = []
+        for j, Q, sch, ta in zip(jobs, Qs, scheds, arrivals):
+            delay = ta - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(api.da_submit(srv, Q, sch, j["replicas"], j["steps"], j["seed"]))
+        outs = [api.da_wait(srv, t) for t in tickets]
+        makespan = time.perf_counter() - t0
+        srv.close()
+        lat = np.array([o["stats"]["t_done"] - o["stats"]["t_submit"] for o in outs])
+        return outs, lat, makespan
+
+    # capacity: everything submitted at once
+    _, _, makespan0 = run_stream([0.0] * n_jobs)
+    rate = 0.8 * n_jobs / makespan0
+    g = np.random.Generator(np.random.PCG64(seed + 1))
+    arrivals = list(np.cumsum(g.exponential(1.0 / rate, size=n_jobs)))
+    outs, lat, makespan = run_stream(arrivals)
+
+    # plain service under the same arrivals: a single FIFO server
+    t_free, plain_lat = 0.0, []
+    for ta, sv in zip(arrivals, service):
+        start = max(ta, t_free)
+        t_free = start + sv
+        plain_lat.append(t_free - ta)
+    plain_lat = np.array(plain_lat)
+    return {
+        "jobs": n_jobs,
+        "sizes": sorted({j["N"] for j in jobs}),
+        "flip_evals": float(work),
+        "batched_capacity_jobs_per_s": n_jobs / makespan0,
+        "arrival_rate_jobs_per_s": rate,
+        "served": {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                   "makespan_s": makespan, "flip_evals_per_s": work / makespan0},
+        "plain_one_job_per_launch": {"p50_s": float(np.percentile(plain_lat, 50)),
+                                     "p99_s": float(np.percentile(plain_lat, 99)),
+                                     "busy_s": busy, "flip_evals_per_s": work / busy},
+        "epoch_steps": epoch_steps, "budget_gb": budget_gb,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +130,8 @@ def main() -> int:
     ap.add_argument("--dtype", type=int, default=None, help="force coupling storage bytes")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-extras", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=24,
+                    help="jobs in the served-stream leg (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -213,6 +282,13 @@ def main() -> int:
             "successes": y, "runs": R, "theta_median": t99["theta"], "r99": t99["r99"],
             "replicas_launched": t99["replicas"], "seconds": t99["tts_s"],
         }
+
+    if not args.skip_extras and args.serve_jobs > 0:
+        t0 = time.perf_counter()
+        result["serve"] = serve_bench(api, workloads, args.serve_jobs, seed=1, budget_gb=16.0,
+                                      epoch_steps=4096)
+        print(f"[bench] served stream: {time.perf_counter() - t0:.1f} s; "
+              f"{json.dumps(result['serve'])}", file=sys.stderr, flush=True)
 
     print(json.dumps(result), flush=True)
     return 0

@@ -131,10 +131,10 @@ LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch,
     const int want_help = launch ? launch->rng_waves : 0;
     bool help = want_help > 0 || (want_help == 0 && latency_bound);
     sh.F = (launch && launch->flips_per_lane) ? launch->flips_per_lane : (latency_bound ? 4 : 8);
-    if (sh.F != 4 && sh.F != 8 && sh.F != 16) sh.F = 8;
+    if (sh.F != 4 && sh.F != 8) sh.F = 8;
     sh.NW = (ctx->N + 64 * sh.F - 1) / (64 * sh.F);
-    while (sh.NW > 16) {  // keep a replica within one workgroup
-        sh.F *= 2;
+    if (sh.NW > 16) {  // keep a replica within one workgroup (N <= 8192)
+        sh.F = 8;
         sh.NW = (ctx->N + 64 * sh.F - 1) / (64 * sh.F);
     }
     const int nblk = (ctx->N + 7) / 8;

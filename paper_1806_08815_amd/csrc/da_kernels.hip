@@ -104,7 +104,7 @@ __device__ __forceinline__ int select_bit(uint32_t m, int r) {
 
 template <int F>
 struct CountBits {
-    static constexpr int value = (F >= 16) ? 5 : (F >= 8 ? 4 : (F >= 4 ? 3 : (F >= 2 ? 2 : 1)));
+    static constexpr int value = F >= 8 ? 4 : (F >= 4 ? 3 : (F >= 2 ? 2 : 1));
 };
 
 template <typename T, int F>
@@ -176,6 +176,7 @@ size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk, int
 template <typename WT, int F, bool TRACE, bool HELP, bool STAGE>
 __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *smem,
                                           const TraceDesc &T) {
+    static_assert(F == 4 || F == 8, "a lane's record holds at most 8 flips");
     constexpr int NB = (F + 7) / 8;   // Philox blocks per lane
     typedef typename VecOf<WT, F>::type RowV;
     const int lane = threadIdx.x & 63;
@@ -377,7 +378,8 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             c = __popc(acc);
             wave_prefix<CountBits<F>::value>(c, excl, wtot);
             if (NW > 1) {
-                rec[par * NW * 64 + g] = acc | (xb << 16);
+                // record: accepted mask | x bits << 8 | inclusive prefix << 16
+                rec[par * NW * 64 + g] = acc | (xb << 8) | ((uint32_t)(excl + c) << 16);
                 if (lane == 0) tot[par * NW + wr] = wtot;
             }
         }
@@ -445,16 +447,14 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 } else {
                     r2 = rec[par * NW * 64 + ws * 64 + lane];
                 }
-                const int c2 = __popc(r2 & 0xFFFFu);
-                int excl2, tot2;
-                wave_prefix<CountBits<F>::value>(c2, excl2, tot2);
-                const uint64_t bal = ballot(excl2 + c2 > jw);
+                // first lane of wave ws whose inclusive prefix passes jw
+                const uint64_t bal = ballot((int)(r2 >> 16) > jw);
                 const int ts = __ffsll((unsigned long long)bal) - 1;
-                const int rloc = jw - readlane(excl2, ts);
                 const uint32_t rs = (uint32_t)readlane((int)r2, ts);
-                bit = select_bit<F>(rs & 0xFFFFu, rloc);
+                const int rloc = jw - ((int)(rs >> 16) - __popc(rs & 0xFFu));
+                bit = select_bit<F>(rs & 0xFFu, rloc);
                 k = (ws * 64 + ts) * F + bit;
-                xk = (rs >> (16 + bit)) & 1;
+                xk = (rs >> (8 + bit)) & 1;
             }
         }
 
@@ -806,7 +806,6 @@ int launch_run_f(const JobDesc &J, int F, const TraceDesc &T, int blocks, int th
     switch (F) {
         case 4: return launch_run_t<WT, 4, TRACE, HELP>(J, T, blocks, threads, lds, stream);
         case 8: return launch_run_t<WT, 8, TRACE, HELP>(J, T, blocks, threads, lds, stream);
-        case 16: return launch_run_t<WT, 16, TRACE, HELP>(J, T, blocks, threads, lds, stream);
         default: return (int)hipErrorInvalidValue;
     }
 }

@@ -75,6 +75,32 @@ def test_batch_matches_alone(api):
             assert np.array_equal(items[a]["out_dev"][k].cpu().numpy(), ref[k]), (a, k)
 
 
+def test_batch_large_n(api):
+    """Batches holding the largest sizes (one replica per workgroup) beside small jobs."""
+    import torch
+    specs = [("sk", 8192, 3, 300, "zeros", 0, 8), ("gauss", 4096, 5, 500, "random", 0, 16),
+             ("sk", 64, 40, 800, "zeros", 0, 16), ("gauss", 6000, 2, 200, "zeros", 4, 4)]
+    items, alone = [], []
+    for a, (kind, N, R, S, init, hint, L) in enumerate(specs):
+        Q, t = _job(kind, N, 70 + a)
+        ctx = api.da_create(Q, hint)
+        sch = api.schedule(t["T_hi"], t["T_lo"], "geometric", L, t["eoff_inc"], init)
+        alone.append(api.da_anneal(ctx, sch, R, S, 3 + a))
+        items.append(dict(ctx=ctx, schedule=sch, replica_base=0, replicas=R, steps=S,
+                          seed=3 + a, out_dev=api.device_outputs(R, N)))
+    api.da_anneal_batch(items)
+    torch.cuda.synchronize()
+    for a, it in enumerate(items):
+        for k in KEYS:
+            assert np.array_equal(it["out_dev"][k].cpu().numpy(), alone[a][k]), (specs[a], k)
+    kind, N, R, S, init, hint, L = specs[0]
+    Q, t = _job(kind, N, 70)
+    ref = oracle.anneal(Q, T_hi=t["T_hi"], T_lo=t["T_lo"], n_levels=L, eoff_inc=t["eoff_inc"],
+                        replica_base=2, replicas=1, steps=S, seed=3)
+    for k in KEYS:
+        assert np.array_equal(items[0]["out_dev"][k].cpu().numpy()[2:3], ref[k]), k
+
+
 def test_server_results_equal_alone(api):
     # a budget that holds only some jobs at once forces queueing and admission
     # as memory frees up; an epoch that does not divide the step counts forces

@@ -64,9 +64,9 @@ def test_energy(api, kind, N, dtype):
 
 @pytest.mark.parametrize("rng", [1, -1])
 @pytest.mark.parametrize("kind,N,dtype,F,rpw", [
-    ("sk", 20, 0, 8, 1), ("sk", 64, 0, 8, 1), ("sk", 64, 2, 4, 2), ("sk", 100, 4, 16, 3),
+    ("sk", 20, 0, 8, 1), ("sk", 64, 0, 8, 1), ("sk", 64, 2, 4, 2), ("sk", 100, 4, 8, 3),
     ("random", 70, 0, 8, 2), ("random", 257, 2, 8, 1), ("gauss", 300, 0, 4, 1),
-    ("sk", 513, 0, 8, 1), ("sk", 1000, 2, 8, 2), ("gauss", 1024, 4, 16, 1),
+    ("sk", 513, 0, 8, 1), ("sk", 1000, 2, 8, 2), ("gauss", 1024, 4, 8, 1),
     ("random_big", 600, 4, 4, 1), ("sk", 1536, 1, 8, 1), ("sk", 1024, 2, 4, 1),
     ("gauss", 2048, 0, 4, 1),
 ])
@@ -152,6 +152,27 @@ def test_replica_base_replay(api):
     sch = api.schedule(20.0, 0.5, eoff_inc=1)
     batch = api.da_anneal_ex(ctx, sch, 0, 24, 2000, 3, api.launch(8, 4, 0, -1))
     for r in (0, 13, 23):
-        one = api.da_anneal_ex(ctx, sch, r, 1, 2000, 3, api.launch(16, 1, 0, 1))
+        one = api.da_anneal_ex(ctx, sch, r, 1, 2000, 3, api.launch(4, 1, 0, 1))
         for k in KEYS:
             assert np.array_equal(one[k][0], batch[k][r])
+
+
+@pytest.mark.parametrize("kind,N,dtype,launch", [
+    ("sk", 8192, 0, None), ("gauss", 8192, 4, None), ("sk", 4096, 2, None),
+    ("sk", 4096, 0, (8, 1, 0, 1)), ("gauss", 5000, 0, None), ("sk", 3001, 0, (4, 1, 0, -1)),
+])
+def test_large_n_trace_parity(api, kind, N, dtype, launch):
+    """The largest sizes: 16 compute waves per replica, ragged last wave."""
+    Q = _q(kind, N, 6)
+    if kind == "gauss":
+        T_hi, T_lo, inc = 3.0 * 2**16, 0.05 * 2**16, 2**16
+    else:
+        T_hi, T_lo, inc = 3.0 * N ** 0.5, 0.1, 1
+    R, S, L = 3, 400, 8
+    ctx = api.da_create(Q, dtype)
+    sch = api.schedule(T_hi, T_lo, "geometric", L, eoff_inc=inc)
+    opts = api.launch(*launch) if launch else None
+    gpu = api.da_anneal_ex(ctx, sch, 1, R, S, 2, opts, trace=True)
+    ref = oracle.anneal(Q, T_hi=T_hi, T_lo=T_lo, n_levels=L, eoff_inc=inc, replica_base=1,
+                        replicas=R, steps=S, seed=2, trace=True)
+    _same(gpu, ref, ("trace_k", "trace_E", "trace_eoff") + KEYS)
