@@ -348,23 +348,39 @@ void BatchRunner::release() {
     h_n = nullptr;
 }
 
+namespace {
+// Calls f(i, j, w_ij) for every pair i < j, w_ij = Q_ij + Q_ji, in 64 x 64
+// tiles so that the transposed reads stay in cache.
+template <class Fn>
+void for_upper_pairs(const int32_t *Q, size_t n, Fn &&f) {
+    constexpr size_t B = 64;
+    for (size_t I = 0; I < n; I += B)
+        for (size_t J = I; J < n; J += B) {
+            const size_t ie = std::min(I + B, n), je = std::min(J + B, n);
+            for (size_t i = I; i < ie; ++i)
+                for (size_t j = std::max(J, i + 1); j < je; ++j)
+                    f(i, j, (int64_t)Q[i * n + j] + (int64_t)Q[j * n + i]);
+        }
+}
+}  // namespace
+
 int derive_storage(const int32_t *Q, int32_t N, int32_t dtype_hint, int32_t &dtype,
                    int32_t &wscale, std::string &err) {
     const size_t n = (size_t)N;
-    int64_t g = 0, maxrow = 0, maxw = 0;
+    int64_t g = 0, maxw = 0;
+    std::vector<int64_t> row(n);
     for (size_t i = 0; i < n; ++i) {
         const int64_t bi = Q[i * n + i];
-        int64_t row = bi < 0 ? -bi : bi;
-        for (size_t j = 0; j < n; ++j) {
-            if (i == j) continue;
-            const int64_t w = (int64_t)Q[i * n + j] + (int64_t)Q[j * n + i];
-            const int64_t aw = w < 0 ? -w : w;
-            row += aw;
-            maxw = std::max(maxw, aw);
-            if (w) g = gcd64(g, w);
-        }
-        maxrow = std::max(maxrow, row);
+        row[i] = bi < 0 ? -bi : bi;
     }
+    for_upper_pairs(Q, n, [&](size_t i, size_t j, int64_t w) {
+        const int64_t aw = w < 0 ? -w : w;
+        row[i] += aw;
+        row[j] += aw;
+        maxw = std::max(maxw, aw);
+        if (w && g != 1) g = gcd64(g, w);
+    });
+    const int64_t maxrow = n ? *std::max_element(row.begin(), row.end()) : 0;
     if (maxrow > (int64_t(1) << 30)) {
         err = "max_i |b_i| + sum_j |W_ij| exceeds 2^30: fields would not fit int32";
         return DA_ERANGE;
@@ -380,6 +396,67 @@ int derive_storage(const int32_t *Q, int32_t N, int32_t dtype_hint, int32_t &dty
     }
     dtype = dt;
     wscale = (int32_t)g;
+    return DA_OK;
+}
+
+namespace {
+template <typename T>
+void fill_padded(const int32_t *Q, size_t n, size_t ld, int64_t g, uint8_t *dst) {
+    T *W = reinterpret_cast<T *>(dst);
+    for_upper_pairs(Q, n, [&](size_t i, size_t j, int64_t w) {
+        const T v = (T)(w / g);
+        W[i * ld + j] = v;
+        W[j * ld + i] = v;
+    });
+}
+}  // namespace
+
+void prepare_matrix(const int32_t *Q, int32_t N, int32_t dtype, int32_t wscale, HostMatrix &hm) {
+    hm.N = N;
+    hm.ld = (N + 63) / 64 * 64;
+    hm.dtype = dtype;
+    hm.wscale = wscale;
+    const size_t n = (size_t)N, ld = (size_t)hm.ld;
+    hm.W.assign(ld * ld * (size_t)dtype, 0);
+    if (dtype == 1) fill_padded<int8_t>(Q, n, ld, wscale, hm.W.data());
+    else if (dtype == 2) fill_padded<int16_t>(Q, n, ld, wscale, hm.W.data());
+    else fill_padded<int32_t>(Q, n, ld, wscale, hm.W.data());
+    hm.b.assign(ld, 0);
+    for (size_t i = 0; i < n; ++i) hm.b[i] = Q[i * n + i];
+}
+
+int create_ctx(const HostMatrix &hm, hipStream_t s, da_ctx **out, std::string &err) {
+    da_ctx *ctx = new (std::nothrow) da_ctx();
+    if (!ctx) {
+        err = "host allocation failed";
+        return DA_ENOMEM;
+    }
+    ctx->N = hm.N;
+    ctx->ld = hm.ld;
+    ctx->dtype = hm.dtype;
+    ctx->wscale = hm.wscale;
+    (void)hipGetDevice(&ctx->device);
+    const char *what = nullptr;
+    hipError_t e = hipMalloc(&ctx->d_W, hm.W.size());
+    if (e != hipSuccess) what = "W allocation";
+    if (!what && (e = hipMalloc(&ctx->d_b, hm.b.size() * 4)) != hipSuccess) what = "b allocation";
+    if (!what && (e = hipMemcpyAsync(ctx->d_W, hm.W.data(), hm.W.size(), hipMemcpyHostToDevice,
+                                     s)) != hipSuccess)
+        what = "W upload";
+    if (!what && (e = hipMemcpyAsync(ctx->d_b, hm.b.data(), hm.b.size() * 4,
+                                     hipMemcpyHostToDevice, s)) != hipSuccess)
+        what = "b upload";
+    // the host image may be freed when this returns
+    if (!what && (e = hipStreamSynchronize(s)) != hipSuccess) what = "upload";
+    if (!what && (e = hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking)) !=
+                     hipSuccess)
+        what = "stream";
+    if (what) {
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        da_destroy(ctx);
+        return (e == hipErrorOutOfMemory) ? DA_ENOMEM : DA_EDEVICE;
+    }
+    *out = ctx;
     return DA_OK;
 }
 
@@ -638,41 +715,12 @@ int da_create(const int32_t *Q, int32_t N, int32_t dtype_hint, da_ctx **out) {
     if (!device_is_gfx950(err)) return fail(nullptr, DA_EDEVICE, err);
 
     int32_t dtype = 0, wscale = 1;
-    int rc0 = derive_storage(Q, N, dtype_hint, dtype, wscale, err);
-    if (rc0) return fail(nullptr, rc0, err);
-    const size_t n = (size_t)N;
-    const int64_t g = wscale;
-
-    da_ctx *ctx = new (std::nothrow) da_ctx();
-    if (!ctx) return fail(nullptr, DA_ENOMEM, "host allocation failed");
-    ctx->N = N;
-    ctx->ld = (N + 63) / 64 * 64;
-    ctx->dtype = dtype;
-    ctx->wscale = (int32_t)g;
-    (void)hipGetDevice(&ctx->device);
-    const size_t ld = (size_t)ctx->ld;
-    std::vector<uint8_t> Wd(ld * ld * (size_t)dtype, 0);
-    for (size_t i = 0; i < n; ++i)
-        for (size_t j = 0; j < n; ++j) {
-            const int64_t w = (i == j) ? 0 : (int64_t)Q[i * n + j] + (int64_t)Q[j * n + i];
-            const int64_t v = w / g;
-            void *dst = Wd.data() + (i * ld + j) * (size_t)dtype;
-            if (dtype == 1) { int8_t t = (int8_t)v; std::memcpy(dst, &t, 1); }
-            else if (dtype == 2) { int16_t t = (int16_t)v; std::memcpy(dst, &t, 2); }
-            else { int32_t t = (int32_t)v; std::memcpy(dst, &t, 4); }
-        }
-    std::vector<int32_t> bd(ld, 0);
-    for (size_t i = 0; i < n; ++i) bd[i] = Q[i * n + i];
-    int rc = check_hip(nullptr, hipMalloc(&ctx->d_W, Wd.size()), "W allocation");
-    if (!rc) rc = check_hip(nullptr, hipMalloc(&ctx->d_b, ld * 4), "b allocation");
-    if (!rc) rc = check_hip(nullptr, hipMemcpy(ctx->d_W, Wd.data(), Wd.size(), hipMemcpyHostToDevice), "W upload");
-    if (!rc) rc = check_hip(nullptr, hipMemcpy(ctx->d_b, bd.data(), ld * 4, hipMemcpyHostToDevice), "b upload");
-    if (!rc) rc = check_hip(nullptr, hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking), "stream");
-    if (rc) {
-        da_destroy(ctx);
-        return rc;
-    }
-    *out = ctx;
+    int rc = derive_storage(Q, N, dtype_hint, dtype, wscale, err);
+    if (rc) return fail(nullptr, rc, err);
+    HostMatrix hm;
+    prepare_matrix(Q, N, dtype, wscale, hm);
+    rc = create_ctx(hm, nullptr, out, err);
+    if (rc) return fail(nullptr, rc, err);
     return DA_OK;
 }
 

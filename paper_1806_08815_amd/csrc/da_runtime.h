@@ -34,9 +34,19 @@ void build_threshold_table(double T, int32_t *thr);
 void build_brackets(const int32_t *thr, LevelHdr &hd, std::vector<uint32_t> &brk);
 // Temperature of level l of a schedule.
 double schedule_temperature(const da_schedule &s, int l);
+// Host image of the tables of a temperature list.
+struct HostTables {
+    std::vector<double> temps;
+    std::vector<int32_t> thr;      // [L][65536]
+    std::vector<LevelHdr> hdr;     // [L]
+    std::vector<uint32_t> brk;
+};
+void build_host_tables(const std::vector<double> &temps, HostTables &ht);
 // Tables for a temperature list (cached per device); nullptr on failure with
-// `err` set.
-std::shared_ptr<LevelTables> get_level_tables(const std::vector<double> &temps, std::string &err);
+// `err` set.  `pre`, when given, must hold the host image of these
+// temperatures' tables and is uploaded instead of building them again.
+std::shared_ptr<LevelTables> get_level_tables(const std::vector<double> &temps, std::string &err,
+                                              const HostTables *pre = nullptr);
 // Device bytes of the tables of L levels with `buckets` brackets in total.
 int64_t level_table_bytes(int32_t L, int64_t buckets);
 
@@ -106,6 +116,20 @@ void append_batch_items(const JobDesc &J, int job_index, std::vector<BatchItem> 
 // error code with `err` set.
 int derive_storage(const int32_t *Q, int32_t N, int32_t dtype_hint, int32_t &dtype,
                    int32_t &wscale, std::string &err);
+
+// Host image of the device copy of W and b: W_ij = (Q_ij + Q_ji) / wscale off
+// the diagonal, zero diagonal, rows padded to ld = N rounded up to 64, dtype
+// bytes per coupling; b = diag(Q), zero padded.
+struct HostMatrix {
+    int32_t N = 0, ld = 0, dtype = 0, wscale = 1;
+    std::vector<uint8_t> W;
+    std::vector<int32_t> b;
+};
+// Fills hm for a storage choice made by derive_storage.
+void prepare_matrix(const int32_t *Q, int32_t N, int32_t dtype, int32_t wscale, HostMatrix &hm);
+// New context holding hm on the current device (uploaded on stream s, which
+// is synchronised before returning).
+int create_ctx(const HostMatrix &hm, hipStream_t s, da_ctx **out, std::string &err);
 
 }  // namespace dapt
 

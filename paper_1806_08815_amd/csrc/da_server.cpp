@@ -1,16 +1,18 @@
 // da_server.cpp -- continuous-batching solve server.
 //
-// Jobs are submitted from any thread.  One worker thread owns the device:
-//   * admission: queued jobs are admitted first-fit, in arrival order, while
-//     their device footprint (da_job_footprint) fits the free budget; an
-//     admitted job gets its own context (coupling matrix, fields, states and
-//     tables stay resident on the device until it finishes);
+// Jobs are submitted from any thread.  Three kinds of work overlap:
+//   * host preparation (two prep threads): the device image of the coupling
+//     matrix and the host image of the level tables of each submitted job;
+//   * admission (the device worker): prepared jobs are admitted first-fit, in
+//     submission order, while their device footprint (da_job_footprint) fits
+//     the free budget; an admitted job's matrix, tables and initial state are
+//     uploaded on an upload stream while the current epoch runs;
 //   * epochs: every resident job advances by up to epoch_steps Monte Carlo
 //     steps, all of them together in one persistent launch of the batched
 //     step kernel (replayed from a captured graph);
-//   * retirement: jobs that reached their step count are copied to host
-//     buffers and their device memory is released, which lets waiting jobs in
-//     at the next epoch boundary.
+//   * retirement: after an epoch, jobs that reached their step count are
+//     copied to host buffers and their device memory is released, which lets
+//     waiting jobs in.
 // The step kernel resumes exactly where an epoch stopped and every random
 // number is keyed by (seed, job-local replica id, global step), so a job's
 // results are the same alone, in any mix, and as a plain da_anneal call.
@@ -35,13 +37,16 @@ using namespace dapt;
 namespace {
 
 constexpr int64_t kDefaultEpochSteps = 8192;
+constexpr int kPrepThreads = 2;
 
 struct Job {
     uint64_t ticket = 0;
-    std::vector<int32_t> Q;
+    std::vector<int32_t> Q;           // until prepared
     da_job spec{};
     int32_t dtype = 0, wscale = 1;
     int64_t footprint = 0;
+    HostMatrix hm;                    // prepared, until uploaded
+    std::unique_ptr<HostTables> ht;   // prepared, until uploaded
     da_ctx *ctx = nullptr;
     std::shared_ptr<LevelTables> tables;
     JobDesc J{};
@@ -67,22 +72,28 @@ struct da_server {
     int device = 0;
     std::chrono::steady_clock::time_point t0;
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
-    std::deque<std::unique_ptr<Job>> queue;
+    std::condition_variable cv_prep, cv_work, cv_done;
+    std::deque<std::unique_ptr<Job>> incoming;        // submitted, not yet prepared
+    std::set<uint64_t> preparing;                     // taken by a prep thread
+    std::deque<std::unique_ptr<Job>> queue;           // prepared, in ticket order
     std::vector<std::unique_ptr<Job>> resident;
     std::map<uint64_t, std::unique_ptr<Job>> finished;
     std::set<uint64_t> retiring;   // left `resident`, results being copied out
     uint64_t next_ticket = 1;
     int64_t used = 0;
     bool stop = false;
+    std::vector<std::thread> prep;
     std::thread worker;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;   // epochs and result copies
+    hipStream_t upload = nullptr;   // admission uploads and state initialisation
     BatchRunner runner;
 
+    void prep_loop();
     void run();
     bool admit_locked(std::vector<Job *> &admitted);
     int start_job(Job &j);
     void retire(std::unique_ptr<Job> &j);
+    bool known_locked(uint64_t ticket) const;
 };
 
 extern "C" int64_t da_job_footprint(int32_t N, int32_t dtype_bytes, int32_t replicas,
@@ -98,23 +109,52 @@ extern "C" int64_t da_job_footprint(int32_t N, int32_t dtype_bytes, int32_t repl
     return w + state + tables + out;
 }
 
-// Creates the job's context, tables and initial state on the server stream.
+// Host preparation of submitted jobs, off the submitting and device threads.
+void da_server::prep_loop() {
+    for (;;) {
+        std::unique_ptr<Job> jp;
+        {
+            std::unique_lock<std::mutex> lock(mu);
+            cv_prep.wait(lock, [&] { return stop || !incoming.empty(); });
+            if (stop) return;
+            jp = std::move(incoming.front());
+            incoming.pop_front();
+            preparing.insert(jp->ticket);
+        }
+        Job &j = *jp;
+        prepare_matrix(j.Q.data(), j.spec.N, j.dtype, j.wscale, j.hm);
+        std::vector<int32_t>().swap(j.Q);
+        j.ht.reset(new HostTables());
+        build_host_tables(schedule_temps(j.spec.schedule), *j.ht);
+        {
+            std::lock_guard<std::mutex> lock(mu);
+            preparing.erase(j.ticket);
+            auto pos = std::upper_bound(
+                queue.begin(), queue.end(), j.ticket,
+                [](uint64_t t, const std::unique_ptr<Job> &q) { return t < q->ticket; });
+            queue.insert(pos, std::move(jp));
+        }
+        cv_work.notify_one();
+    }
+}
+
+// Device context, tables and initial state of an admitted job, on the upload
+// stream (the caller synchronises it before the job's first epoch).
 int da_server::start_job(Job &j) {
     da_ctx *ctx = nullptr;
-    int rc = da_create(j.Q.data(), j.spec.N, j.spec.dtype_hint, &ctx);
-    if (rc) {
-        j.err = da_last_error(nullptr);
-        return rc;
-    }
+    int rc = create_ctx(j.hm, upload, &ctx, j.err);
+    HostMatrix().W.swap(j.hm.W);
+    if (rc) return rc;
     j.ctx = ctx;
-    j.tables = get_level_tables(schedule_temps(j.spec.schedule), j.err);
+    j.tables = get_level_tables(schedule_temps(j.spec.schedule), j.err, j.ht.get());
+    j.ht.reset();
     if (!j.tables) return DA_ENOMEM;
     ctx->keep_tables = j.tables;
     if (!ctx->st.ensure(j.spec.replicas, ctx->ld, j.err)) return DA_ENOMEM;
     const LaunchShape sh = batch_shape(ctx);
     j.J = make_job(ctx, *j.tables, j.spec.replicas, 0u, j.spec.seed, j.spec.steps,
                    j.spec.schedule, sh);
-    rc = init_state(ctx, j.J, j.spec.schedule.init, stream);
+    rc = init_state(ctx, j.J, j.spec.schedule.init, upload);
     if (rc) j.err = ctx->err;
     return rc;
 }
@@ -169,53 +209,44 @@ void da_server::retire(std::unique_ptr<Job> &jp) {
     j.stats.t_done = now_s(t0);
 }
 
+// The device worker.  Each pass: admit and upload new jobs (overlapping the
+// epoch in flight), finish that epoch, retire, then launch the next epoch
+// without waiting for it.
 void da_server::run() {
     (void)hipSetDevice(device);
+    std::vector<Job *> in_epoch;
+    std::vector<JobDesc> jobs;
+    bool inflight = false;
     for (;;) {
         std::vector<Job *> admitted;
         {
             std::unique_lock<std::mutex> lock(mu);
-            cv_work.wait(lock, [&] { return stop || !queue.empty() || !resident.empty(); });
+            if (!inflight)
+                cv_work.wait(lock, [&] { return stop || !queue.empty() || !resident.empty(); });
             if (stop) {
-                for (auto &q : queue) {
-                    q->status = DA_ENOTFOUND;
-                    q->err = "server shut down before the job was admitted";
-                }
+                for (auto *dq : {&incoming, &queue})
+                    for (auto &q : *dq) {
+                        q->status = DA_ENOTFOUND;
+                        q->err = "server shut down before the job was admitted";
+                    }
+                incoming.clear();
                 queue.clear();
-                if (resident.empty()) break;
+                if (resident.empty() && !inflight) break;
+            } else {
+                admit_locked(admitted);
             }
-            admit_locked(admitted);
         }
         for (Job *j : admitted) {
             j->status = start_job(*j);
             j->stats.device_bytes = j->footprint;
         }
-        // one epoch over every resident job
-        std::vector<JobDesc> jobs;
-        std::vector<BatchItem> items;
-        std::vector<Job *> in_epoch;
-        {
-            std::lock_guard<std::mutex> lock(mu);
-            for (auto &jp : resident) {
-                Job &j = *jp;
-                if (j.status != DA_OK || j.done_steps >= j.spec.steps) continue;
-                JobDesc J = j.J;
-                J.s0 = j.done_steps;
-                J.s1 = std::min(j.spec.steps, j.done_steps + epoch_steps);
-                append_batch_items(J, (int)jobs.size(), items);
-                jobs.push_back(J);
-                in_epoch.push_back(&j);
-            }
-        }
-        if (!jobs.empty()) {
+        if (inflight) {
             std::string err;
-            int rc = runner.run(jobs, items, stream, err);
-            if (rc == DA_OK) {
-                const hipError_t e = hipStreamSynchronize(stream);
-                if (e != hipSuccess) {
-                    rc = DA_EDEVICE;
-                    err = hipGetErrorString(e);
-                }
+            int rc = DA_OK;
+            const hipError_t e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) {
+                rc = DA_EDEVICE;
+                err = hipGetErrorString(e);
             }
             for (size_t a = 0; a < in_epoch.size(); ++a) {
                 Job &j = *in_epoch[a];
@@ -227,6 +258,16 @@ void da_server::run() {
                     j.stats.epochs += 1;
                 }
             }
+            inflight = false;
+        }
+        if (!admitted.empty()) {
+            const hipError_t e = hipStreamSynchronize(upload);
+            if (e != hipSuccess)
+                for (Job *j : admitted)
+                    if (j->status == DA_OK) {
+                        j->status = DA_EDEVICE;
+                        j->err = hipGetErrorString(e);
+                    }
         }
         // retire finished (or failed) jobs and wake their waiters
         std::vector<std::unique_ptr<Job>> leaving;
@@ -244,17 +285,57 @@ void da_server::run() {
         }
         for (auto &jp : leaving) retire(jp);
         if (!leaving.empty()) {
-            std::lock_guard<std::mutex> lock(mu);
-            for (auto &jp : leaving) {
-                used -= jp->footprint;
-                const uint64_t t = jp->ticket;
-                retiring.erase(t);
-                finished[t] = std::move(jp);
+            {
+                std::lock_guard<std::mutex> lock(mu);
+                for (auto &jp : leaving) {
+                    used -= jp->footprint;
+                    const uint64_t t = jp->ticket;
+                    retiring.erase(t);
+                    finished[t] = std::move(jp);
+                }
             }
             cv_done.notify_all();
         }
+        // next epoch over every resident job, launched without waiting
+        in_epoch.clear();
+        jobs.clear();
+        std::vector<BatchItem> items;
+        {
+            std::lock_guard<std::mutex> lock(mu);
+            for (auto &jp : resident) {
+                Job &j = *jp;
+                JobDesc J = j.J;
+                J.s0 = j.done_steps;
+                J.s1 = std::min(j.spec.steps, j.done_steps + epoch_steps);
+                append_batch_items(J, (int)jobs.size(), items);
+                jobs.push_back(J);
+                in_epoch.push_back(&j);
+            }
+        }
+        if (!jobs.empty()) {
+            std::string err;
+            const int rc = runner.run(jobs, items, stream, err);
+            if (rc) {
+                for (Job *j : in_epoch) {
+                    j->status = rc;
+                    j->err = err;
+                }
+            } else {
+                inflight = true;
+            }
+        }
     }
     cv_done.notify_all();
+}
+
+bool da_server::known_locked(uint64_t ticket) const {
+    if (finished.count(ticket) || retiring.count(ticket) || preparing.count(ticket)) return true;
+    for (auto *dq : {&incoming, &queue})
+        for (auto &q : *dq)
+            if (q->ticket == ticket) return true;
+    for (auto &q : resident)
+        if (q->ticket == ticket) return true;
+    return false;
 }
 
 extern "C" {
@@ -272,7 +353,9 @@ int da_server_create(size_t hbm_budget, const da_server_opts *opts, da_server **
         srv->max_resident = std::min<int32_t>(opts->max_resident, BatchRunner::kCapJobs);
     srv->t0 = std::chrono::steady_clock::now();
     (void)hipGetDevice(&srv->device);
-    if (hipStreamCreateWithFlags(&srv->stream, hipStreamNonBlocking) != hipSuccess) {
+    if (hipStreamCreateWithFlags(&srv->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&srv->upload, hipStreamNonBlocking) != hipSuccess) {
+        if (srv->stream) (void)hipStreamDestroy(srv->stream);
         delete srv;
         return fail(nullptr, DA_EDEVICE, "server stream creation failed");
     }
@@ -280,9 +363,11 @@ int da_server_create(size_t hbm_budget, const da_server_opts *opts, da_server **
     const int rc = srv->runner.prepare(err);
     if (rc) {
         (void)hipStreamDestroy(srv->stream);
+        (void)hipStreamDestroy(srv->upload);
         delete srv;
         return fail(nullptr, rc, err);
     }
+    for (int t = 0; t < kPrepThreads; ++t) srv->prep.emplace_back([srv] { srv->prep_loop(); });
     srv->worker = std::thread([srv] { srv->run(); });
     *out = srv;
     return DA_OK;
@@ -293,6 +378,7 @@ int da_submit(da_server *srv, const da_job *job, uint64_t *ticket) {
     if (job->N < 1 || job->N > DA_MAX_N) return fail(nullptr, DA_EINVAL, "N must be in [1, 8192]");
     if (job->replicas < 1 || job->steps < 0 || job->steps >= (int64_t(1) << 31))
         return fail(nullptr, DA_EINVAL, "bad replicas or steps");
+    const double t_submit = now_s(srv->t0);
     std::string err;
     int rc = validate_schedule(&job->schedule, err);
     if (rc) return fail(nullptr, rc, err);
@@ -308,11 +394,11 @@ int da_submit(da_server *srv, const da_job *job, uint64_t *ticket) {
     {
         std::lock_guard<std::mutex> lock(srv->mu);
         j->ticket = srv->next_ticket++;
-        j->stats.t_submit = now_s(srv->t0);
+        j->stats.t_submit = t_submit;
         *ticket = j->ticket;
-        srv->queue.push_back(std::move(j));
+        srv->incoming.push_back(std::move(j));
     }
-    srv->cv_work.notify_one();
+    srv->cv_prep.notify_one();
     return DA_OK;
 }
 
@@ -322,14 +408,7 @@ static int collect(da_server *srv, uint64_t ticket, da_result *out, da_job_stats
     std::unique_ptr<Job> j;
     {
         std::unique_lock<std::mutex> lock(srv->mu);
-        auto known = [&] {
-            if (srv->finished.count(ticket) || srv->retiring.count(ticket)) return true;
-            for (auto &q : srv->queue)
-                if (q->ticket == ticket) return true;
-            for (auto &q : srv->resident)
-                if (q->ticket == ticket) return true;
-            return false;
-        };
+        auto known = [&] { return srv->known_locked(ticket); };
         if (!known()) return fail(nullptr, DA_ENOTFOUND, "unknown or already collected ticket");
         if (wait) {
             srv->cv_done.wait(lock, [&] { return srv->finished.count(ticket) > 0 || !known(); });
@@ -368,10 +447,21 @@ void da_server_destroy(da_server *srv) {
         std::lock_guard<std::mutex> lock(srv->mu);
         srv->stop = true;
     }
+    srv->cv_prep.notify_all();
     srv->cv_work.notify_all();
+    for (auto &t : srv->prep)
+        if (t.joinable()) t.join();
     if (srv->worker.joinable()) srv->worker.join();
+    {
+        // jobs a prep thread finished after the worker stopped admitting
+        std::lock_guard<std::mutex> lock(srv->mu);
+        srv->queue.clear();
+        srv->incoming.clear();
+    }
+    srv->cv_done.notify_all();
     srv->runner.release();
     if (srv->stream) (void)hipStreamDestroy(srv->stream);
+    if (srv->upload) (void)hipStreamDestroy(srv->upload);
     delete srv;
 }
 

@@ -20,14 +20,27 @@ namespace {
 constexpr int64_t kThrMax = int64_t(1) << 30;
 }
 
+namespace {
+// ln U_u for every draw, computed once: a level's table is then one product
+// per entry, the same product -T * ln(U_u) either way.
+const double *log_u_table() {
+    static const std::vector<double> t = [] {
+        std::vector<double> v(65536);
+        for (int u = 0; u < 65536; ++u) v[(size_t)u] = std::log(((double)u + 0.5) / 65536.0);
+        return v;
+    }();
+    return t.data();
+}
+}  // namespace
+
 void build_threshold_table(double T, int32_t *thr) {
+    const double *lnU = log_u_table();
     for (int u = 0; u < 65536; ++u) {
         if (!(T > 0.0)) {
             thr[u] = -1;
             continue;
         }
-        const double U = ((double)u + 0.5) / 65536.0;
-        const double y = -T * std::log(U);
+        const double y = -T * lnU[u];
         const double c = std::ceil(y) - 1.0;
         int64_t t = (c >= (double)kThrMax) ? kThrMax : (int64_t)c;
         if (t < -1) t = -1;
@@ -104,7 +117,21 @@ std::mutex g_cache_mu;
 std::map<CacheKey, std::weak_ptr<LevelTables>> g_cache;
 }  // namespace
 
-std::shared_ptr<LevelTables> get_level_tables(const std::vector<double> &temps, std::string &err) {
+void build_host_tables(const std::vector<double> &temps, HostTables &ht) {
+    const size_t L = temps.size();
+    ht.temps = temps;
+    ht.thr.resize(L * 65536);
+    ht.hdr.resize(L);
+    ht.brk.clear();
+    for (size_t l = 0; l < L; ++l) {
+        build_threshold_table(temps[l], ht.thr.data() + l * 65536);
+        build_brackets(ht.thr.data() + l * 65536, ht.hdr[l], ht.brk);
+    }
+    if (ht.brk.empty()) ht.brk.push_back(0);
+}
+
+std::shared_ptr<LevelTables> get_level_tables(const std::vector<double> &temps, std::string &err,
+                                              const HostTables *pre) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) {
         err = "hipGetDevice failed";
@@ -117,27 +144,25 @@ std::shared_ptr<LevelTables> get_level_tables(const std::vector<double> &temps, 
     if (it != g_cache.end()) {
         if (auto sp = it->second.lock()) return sp;
     }
+    HostTables own;
+    if (!pre || pre->temps != temps) {
+        build_host_tables(temps, own);
+        pre = &own;
+    }
     auto lt = std::make_shared<LevelTables>();
     lt->temps = temps;
     lt->L = (int32_t)temps.size();
-    std::vector<int32_t> thr((size_t)lt->L * 65536);
-    std::vector<uint32_t> brk;
-    lt->hdr.resize((size_t)lt->L);
-    for (int l = 0; l < lt->L; ++l) {
-        build_threshold_table(temps[(size_t)l], thr.data() + (size_t)l * 65536);
-        build_brackets(thr.data() + (size_t)l * 65536, lt->hdr[(size_t)l], brk);
-    }
-    if (brk.empty()) brk.push_back(0);
-    const size_t thr_b = thr.size() * 4, hdr_b = lt->hdr.size() * sizeof(LevelHdr),
-                 brk_b = brk.size() * 4;
+    lt->hdr = pre->hdr;
+    const size_t thr_b = pre->thr.size() * 4, hdr_b = pre->hdr.size() * sizeof(LevelHdr),
+                 brk_b = pre->brk.size() * 4;
     if (hipMalloc(&lt->d_thr, thr_b) != hipSuccess || hipMalloc(&lt->d_hdr, hdr_b) != hipSuccess ||
         hipMalloc(&lt->d_brk, brk_b) != hipSuccess) {
         err = "out of device memory for level tables";
         return nullptr;
     }
-    if (hipMemcpy(lt->d_thr, thr.data(), thr_b, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(lt->d_hdr, lt->hdr.data(), hdr_b, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(lt->d_brk, brk.data(), brk_b, hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(lt->d_thr, pre->thr.data(), thr_b, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(lt->d_hdr, pre->hdr.data(), hdr_b, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(lt->d_brk, pre->brk.data(), brk_b, hipMemcpyHostToDevice) != hipSuccess) {
         err = "upload of level tables failed";
         return nullptr;
     }
