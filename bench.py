@@ -48,10 +48,115 @@ def cpu_info():
     return model, os.cpu_count()
 
 
+KERNEL_SOURCES = ("paper_1806_08815_amd/csrc/da_kernels.hip", "paper_1806_08815_amd/csrc/da_internal.h")
+
+
+def measured_traffic(workload: str, launch: dict):
+    """HBM bytes per launch of the step kernel from the committed memory-counter
+    summary of this workload, or None when the kernel source or the launch
+    shape differs from the one the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"pmc_k_run_{workload}.md")
+    try:
+        with open(path) as f:
+            line = next(l for l in f if l.startswith("machine-readable:"))
+    except (OSError, StopIteration):
+        return None
+    rec = json.loads(line.split(":", 1)[1])
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, name), "rb") as f:
+            h.update(f.read())
+    if rec.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    if any(launch.get(k) != v for k, v in rec["launch"].items()):
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
 def describe(w):
     return (f"{w.name}: {w.kind} N={w.N}, {w.replicas} replicas x {w.steps} MC steps, "
             f"{w.schedule} T {w.T_hi:g}->{w.T_lo:g} ({w.n_levels} levels), "
             f"E_off increment {w.eoff_inc}, {w.init} start, Philox seed {w.seed}")
+
+
+def throughput_leg(api, workloads, name: str, steps=None):
+    """One full anneal of another workload in its autotuned launch (after one
+    warm-up anneal): flip-evals/s, ns per step and row-stream bytes."""
+    import torch
+    w = workloads.WORKLOADS[name]
+    Q, _ = w.instance()
+    ctx = api.da_create(Q, w.dtype_hint)
+    info = ctx.info()
+    sch = api.schedule(w.T_hi, w.T_lo, w.schedule, w.n_levels, w.eoff_inc, w.init)
+    S = w.steps if steps is None else steps
+    out = api.device_outputs(w.replicas, w.N)
+    stream = torch.cuda.current_stream()
+    api.da_anneal_async(ctx, sch, 0, w.replicas, S, w.seed, None, out, stream)
+    torch.cuda.synchronize()
+    api.da_reset_kernel_stats(ctx)
+    t0 = time.perf_counter()
+    api.da_anneal_async(ctx, sch, 0, w.replicas, S, w.seed, None, out, stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ks = api.da_last_kernel_stats(ctx)
+    kern = ks["kernel_ms"] / 1e3
+    acc = float(out["n_accept"].sum().item())
+    row_bytes = acc * w.N * info["dtype"]
+    return {
+        "workload": describe(w), "replicas": w.replicas, "mc_steps": S,
+        "coupling_storage": f"int{8 * info['dtype']}",
+        "flip_evals_per_s": w.replicas * S * w.N / wall,
+        "kernel_ms": kern * 1e3, "ns_per_mc_step": kern / S * 1e9,
+        "accepted_step_fraction": acc / (w.replicas * S),
+        "row_stream_GBps": row_bytes / kern / 1e9,
+        "launch": {k: ks[k] for k in ("blocks", "threads", "flips_per_lane",
+                                      "replicas_per_block", "rng_waves")},
+    }
+
+
+def pt_leg(api, workloads, rounds: int):
+    """Parallel tempering at the full ladder and chain count, a bounded number
+    of rounds (the rate is per round, so the full 10^4 rounds scale linearly)."""
+    import numpy as np
+    p = workloads.PT_WORKLOAD
+    Q, _ = workloads.make_instance(p["kind"], p["N"], p["instance_seed"])
+    temps = workloads.pt_temperatures(p["M"], p["T_lo"], p["T_hi"], p["temp_scale"])
+    ctx = api.da_create(Q)
+    api.da_pt(ctx, temps, p["chains"], 2, p["steps_per_round"], p["eoff_inc"], p["seed"])
+    t0 = time.perf_counter()
+    out = api.da_pt(ctx, temps, p["chains"], rounds, p["steps_per_round"], p["eoff_inc"],
+                    p["seed"])
+    dt = time.perf_counter() - t0
+    R = p["M"] * p["chains"]
+    fe = R * rounds * p["steps_per_round"] * p["N"]
+    return {
+        "workload": f"{p['name']}: {p['kind']} N={p['N']}, {p['chains']} chains x M={p['M']} "
+                    f"temperatures, K={p['steps_per_round']} steps per round, random start",
+        "rounds_timed": rounds, "rounds_full": p["rounds"], "seconds": dt,
+        "flip_evals_per_s": fe / dt, "exchange_decisions": int(rounds * p["chains"] * (p["M"] - 1)),
+        "swaps_accepted": int(np.asarray(out["n_swaps"]).sum()),
+        "full_run_estimate_s": dt / rounds * p["rounds"],
+    }
+
+
+def cpu_all_cores(oracle, Q, w, threads: int):
+    """The oracle on `threads` replicas at once (one replica per thread; the C
+    loop releases the interpreter lock), the same schedule as the GPU run."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(r):
+        return oracle.anneal(Q, T_hi=w.T_hi, T_lo=w.T_lo,
+                             kind=0 if w.schedule == "geometric" else 1,
+                             n_levels=w.n_levels, eoff_inc=w.eoff_inc,
+                             init=0 if w.init == "zeros" else 1, replicas=1, replica_base=r,
+                             steps=w.steps, seed=w.seed)
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        outs = list(ex.map(one, range(threads)))
+    dt = time.perf_counter() - t0
+    return threads * w.steps * w.N / dt, dt, outs
 
 
 def serve_bench(api, workloads, n_jobs: int, seed: int, budget_gb: float, epoch_steps: int,
@@ -145,6 +250,9 @@ def main() -> int:
     ap.add_argument("--skip-extras", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=24,
                     help="jobs in the served-stream leg (0 skips it)")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="after the timed region, one plain device copy of this many MiB "
+                         "(the known-size reference for memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -197,6 +305,16 @@ def main() -> int:
           f"per launch; {value:.4g} flip-evals/s; {achieved:.1f} GB/s row stream",
           file=sys.stderr, flush=True)
 
+    # latency floor: a dependent chain of row fetches alone, same matrix size and
+    # element type, one chain per replica (no flip work)
+    floor_ns = None
+    if info["dtype"] in (2, 4):
+        waves = max(1, -(-N // 512))
+        floor_ns = api.da_probe_row_stream(N, N, info["dtype"], R, waves, 20_000)["ns_per_step"]
+
+    launch = {k: ks[k] for k in ("blocks", "threads", "flips_per_lane", "replicas_per_block",
+                                 "w_in_lds", "rng_waves")}
+    traffic = measured_traffic(args.workload, launch)
     result = {
         "metric": METRIC,
         "value": value,
@@ -215,8 +333,7 @@ def main() -> int:
             "N": N, "replicas": R, "mc_steps": S,
             "coupling_storage": f"int{8 * info['dtype']}",
             "wscale": info["wscale"],
-            "launch": {k: ks[k] for k in ("blocks", "threads", "flips_per_lane",
-                                          "replicas_per_block", "w_in_lds")},
+            "launch": launch,
         },
         "roofline": {
             "bound": "hbm",
@@ -224,14 +341,25 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
             "kernel": "k_run (step kernel)",
             "kernel_ms": kernel_s * 1e3,
             "bytes_per_launch": row_bytes,
             "accepted_step_fraction": float(n_acc.sum()) / (R * S),
             "ns_per_mc_step": kernel_s / S * 1e9,
+            "row_fetch_chain_ns": floor_ns,
+            "fetch_chain_over_step": (floor_ns / (kernel_s / S * 1e9)) if floor_ns else None,
         },
     }
+
+    if args.copy_probe_mb > 0:
+        nbytes = args.copy_probe_mb << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     if not args.skip_cpu:
         import oracle
@@ -246,17 +374,22 @@ def main() -> int:
         same = (int(ref["best_E"][0]) == int(best_E[0]) and int(ref["n_accept"][0]) == int(n_acc[0])
                 and np.array_equal(ref["best_x"][0], best_x0)
                 and np.array_equal(ref["final_x"][0], final_x0))
+        threads = max(1, min(ncpu or 1, 16, R))
+        v_all, t_all, outs = cpu_all_cores(oracle, Q, w, threads)
+        same_all = all(int(o["best_E"][0]) == int(best_E[r]) for r, o in enumerate(outs))
         result["cpu_baseline"] = {
-            "value": S * N / t_cpu,
+            "value": v_all,
             "unit": "flip-evals/s",
-            "cores": 1,
+            "cores": threads,
             "kind": "oracle",
-            "sample": f"replica 0 of {R}, all {S} MC steps of the same schedule, "
-                      f"{t_cpu:.1f} s single-threaded on {model} ({ncpu} host CPUs)",
-            "matches_gpu_replica0": bool(same),
+            "sample": f"replicas 0..{threads - 1} of {R}, all {S} MC steps of the same schedule, "
+                      f"one replica per thread on {threads} threads, {t_all:.1f} s wall on "
+                      f"{model} ({ncpu} host CPUs)",
+            "single_core": {"value": S * N / t_cpu, "seconds": t_cpu, "replica": 0},
+            "matches_gpu_replicas": bool(same and same_all),
         }
-        print(f"[bench] oracle: {t_cpu:.1f} s, parity with GPU replica 0: {same}",
-              file=sys.stderr, flush=True)
+        print(f"[bench] oracle: 1 core {t_cpu:.1f} s, {threads} threads {t_all:.1f} s, parity "
+              f"with GPU replicas: {same and same_all}", file=sys.stderr, flush=True)
 
     if not args.skip_extras:
         # one launch per replica, on the same stream, same outputs per replica
@@ -295,6 +428,14 @@ def main() -> int:
             "successes": y, "runs": R, "theta_median": t99["theta"], "r99": t99["r99"],
             "replicas_launched": t99["replicas"], "seconds": t99["tts_s"],
         }
+
+    if not args.skip_extras:
+        t0 = time.perf_counter()
+        result["sk_gaussian_1024"] = throughput_leg(api, workloads, "sk-gaussian-1024")
+        result["pt"] = pt_leg(api, workloads, rounds=20)
+        print(f"[bench] gaussian and PT legs: {time.perf_counter() - t0:.1f} s; "
+              f"{json.dumps(result['sk_gaussian_1024'])} {json.dumps(result['pt'])}",
+              file=sys.stderr, flush=True)
 
     if not args.skip_extras and args.serve_jobs > 0:
         t0 = time.perf_counter()

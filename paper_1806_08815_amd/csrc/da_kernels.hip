@@ -89,17 +89,38 @@ __device__ __forceinline__ void wave_prefix(int c, int &excl, int &total) {
     }
 }
 
-// Position of the r-th (0-based) set bit of the F-bit mask m (branch-free).
+// Position of the r-th (0-based) set bit of a 4-bit mask m, for every (m, r):
+// entry 4 (m & 7) + r of half m >> 3, two bits each.
+constexpr uint64_t select4_half(int half) {
+    uint64_t t = 0;
+    for (int m = 8 * half; m < 8 * half + 8; ++m)
+        for (int r = 0; r < 4; ++r) {
+            int cnt = 0, pos = 0;
+            for (int q = 0; q < 4; ++q)
+                if ((m >> q) & 1) {
+                    if (cnt == r) pos = q;
+                    ++cnt;
+                }
+            t |= (uint64_t)pos << (2 * ((m - 8 * half) * 4 + r));
+        }
+    return t;
+}
+
+__device__ __forceinline__ int select_bit4(uint32_t m, int r) {
+    constexpr uint64_t lo = select4_half(0), hi = select4_half(1);
+    const uint64_t t = (m & 8u) ? hi : lo;
+    return (int)((t >> (2 * (((m & 7u) << 2) + (uint32_t)r))) & 3u);
+}
+
+// Position of the r-th (0-based) set bit of the F-bit mask m, r < popc(m)
+// (table lookups, no loop over bits).
 template <int F>
 __device__ __forceinline__ int select_bit(uint32_t m, int r) {
-    int pos = 0, cnt = 0;
-#pragma unroll
-    for (int q = 0; q < F; ++q) {
-        const int b = (m >> q) & 1;
-        pos = (b && cnt == r) ? q : pos;
-        cnt += b;
-    }
-    return pos;
+    static_assert(F == 4 || F == 8, "4 or 8 flips per lane");
+    if (F == 4) return select_bit4(m, r);
+    const uint32_t low = m & 15u;
+    const int c = __popc(low);
+    return r < c ? select_bit4(low, r) : 4 + select_bit4(m >> 4, r - c);
 }
 
 template <int F>
@@ -186,6 +207,9 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     const int NH = HELP ? J.NH : 0;
     const int ncomp = J.RPW * NW;
     const bool helper = HELP && wave >= ncomp;
+    // compute waves first: the random-number waves share SIMDs with some of
+    // them and must not delay the step's critical path
+    if (HELP && !helper) __builtin_amdgcn_s_setprio(2);
     const int slot = helper ? (wave - ncomp) / NH : wave / NW;
     const int wr = helper ? (wave - ncomp) - slot * NH : wave - slot * NW;
     const int g = wr * 64 + lane;
@@ -462,9 +486,12 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             // 4. fetch row k of W (the step's only bulk traffic) and apply the
             // flip: state, energy, every field
             RowV raw;
-            if (J.w_lds) raw = *reinterpret_cast<const RowV *>(Wl + (size_t)k * ld + col0);
-            else raw = *reinterpret_cast<const RowV *>(reinterpret_cast<const WT *>(J.W) +
-                                                        (size_t)k * ld + col0);
+            // address-space-typed loads: a generic pointer would make this one
+            // flat load that waits on both the vector and the LDS counters
+            typedef __attribute__((address_space(3))) const RowV LdsRowV;
+            typedef __attribute__((address_space(1))) const RowV GlobalRowV;
+            if (J.w_lds) raw = *(LdsRowV *)(Wl + (size_t)k * ld + col0);
+            else raw = *(GlobalRowV *)(reinterpret_cast<const WT *>(J.W) + (size_t)k * ld + col0);
             const int delta = xk ? -1 : 1;
             const bool owner = g == (k / F);
             if (NW > 1 && owner) {
