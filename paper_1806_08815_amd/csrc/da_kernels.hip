@@ -445,15 +445,6 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 dk = readlane(dsel, ts);
             }
         } else {
-            // the previous step's energy change (written by its owner lane)
-            if (pend) {
-                E += (int64_t)__builtin_amdgcn_readfirstlane(dEp);
-                const bool better = E < bE;
-                bE = better ? E : bE;
-                bxb = better ? xb : bxb;
-                if (TRACE && active && g == 0) T.E[rr * T.stride + (s - 1 - s0)] = E;
-                pend = false;
-            }
             const int scan = row16_incl_scan(tw);
             m = readlane(scan, NW - 1);
             if (m > 0) {
@@ -482,16 +473,28 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             }
         }
 
+        // 4. fetch row k of W (the step's only bulk traffic), then, while it
+        // is in flight, finish the previous step's energy and best state
+        RowV raw;
         if (m > 0) {
-            // 4. fetch row k of W (the step's only bulk traffic) and apply the
-            // flip: state, energy, every field
-            RowV raw;
             // address-space-typed loads: a generic pointer would make this one
             // flat load that waits on both the vector and the LDS counters
             typedef __attribute__((address_space(3))) const RowV LdsRowV;
             typedef __attribute__((address_space(1))) const RowV GlobalRowV;
             if (J.w_lds) raw = *(LdsRowV *)(Wl + (size_t)k * ld + col0);
             else raw = *(GlobalRowV *)(reinterpret_cast<const WT *>(J.W) + (size_t)k * ld + col0);
+        }
+        if (NW > 1 && pend) {
+            // the previous step's energy change (written by its owner lane)
+            E += (int64_t)__builtin_amdgcn_readfirstlane(dEp);
+            const bool better = E < bE;
+            bE = better ? E : bE;
+            bxb = better ? xb : bxb;
+            if (TRACE && active && g == 0) T.E[rr * T.stride + (s - 1 - s0)] = E;
+            pend = false;
+        }
+        if (m > 0) {
+            // apply the flip: state, energy, every field
             const int delta = xk ? -1 : 1;
             const bool owner = g == (k / F);
             if (NW > 1 && owner) {
