@@ -140,6 +140,33 @@ def pt_leg(api, workloads, rounds: int):
     }
 
 
+def checkpoint_leg(api, workloads, name: str, cut_frac: float = 0.5):
+    """Stop the workload's anneal part-way, snapshot it to host memory, resume in a
+    fresh context, and compare with the uninterrupted run."""
+    import numpy as np
+    w = workloads.WORKLOADS[name]
+    Q, _ = w.instance()
+    sch = api.schedule(w.T_hi, w.T_lo, w.schedule, w.n_levels, w.eoff_inc, w.init)
+    R, S = w.replicas, w.steps
+    cut = int(S * cut_frac)
+    a = api.da_create(Q, w.dtype_hint)
+    whole = api.da_anneal_ex(a, sch, 0, R, S, w.seed)
+    api.da_anneal_steps(a, sch, 0, R, S, 0, cut, w.seed)
+    t0 = time.perf_counter()
+    snap = api.da_state_save(a, R)
+    t_save = time.perf_counter() - t0
+    a.close()
+    b = api.da_create(Q, w.dtype_hint)
+    t0 = time.perf_counter()
+    api.da_state_load(b, snap)
+    t_load = time.perf_counter() - t0
+    rest = api.da_anneal_steps(b, sch, 0, R, S, cut, S, w.seed)
+    same = all(np.array_equal(rest[k], whole[k])
+               for k in ("best_x", "best_E", "final_x", "final_E", "n_accept"))
+    return {"workload": name, "cut_step": cut, "snapshot_bytes": int(snap.nbytes),
+            "save_ms": t_save * 1e3, "load_ms": t_load * 1e3, "resumed_equals_whole": bool(same)}
+
+
 def cpu_all_cores(oracle, Q, w, threads: int):
     """The oracle on `threads` replicas at once (one replica per thread; the C
     loop releases the interpreter lock), the same schedule as the GPU run."""
@@ -433,8 +460,10 @@ def main() -> int:
         t0 = time.perf_counter()
         result["sk_gaussian_1024"] = throughput_leg(api, workloads, "sk-gaussian-1024")
         result["pt"] = pt_leg(api, workloads, rounds=20)
+        result["checkpoint"] = checkpoint_leg(api, workloads, args.workload)
         print(f"[bench] gaussian and PT legs: {time.perf_counter() - t0:.1f} s; "
-              f"{json.dumps(result['sk_gaussian_1024'])} {json.dumps(result['pt'])}",
+              f"{json.dumps(result['sk_gaussian_1024'])} {json.dumps(result['pt'])} "
+              f"{json.dumps(result['checkpoint'])}",
               file=sys.stderr, flush=True)
 
     if not args.skip_extras and args.serve_jobs > 0:

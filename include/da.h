@@ -210,6 +210,57 @@ typedef struct da_batch_item {
  * be distinct and live on the current device.  Errors as da_anneal_async. */
 int da_anneal_batch(const da_batch_item *items, int32_t count, void *stream);
 
+/* ---- checkpoint / resume ------------------------------------------------
+ * A DA step (Algorithm 2, Sec. II.B) is a function of the replica state, the
+ * step index, the replica id and the seed alone (counter-based draws), so a
+ * run may stop after any step and continue later -- in another context, on
+ * another device, after the process restarted -- with results identical to an
+ * uninterrupted run. */
+
+/* Runs steps [step_begin, step_end) of a total_steps-step anneal of replicas
+ * replica_base .. replica_base+replicas-1.  step_begin = 0 starts from the
+ * schedule's initial state; step_begin > 0 continues from the state the
+ * context holds, which must be that of the same replicas after exactly
+ * step_begin steps (left by the previous da_anneal_steps call on the context,
+ * or by da_state_load).  The level of step s is floor(s L / total_steps), so
+ * pieces of one run must all pass the same total_steps, schedule and seed.
+ * `out` (nullable) receives best/final states, energies and accepted counts as
+ * of step_end.  Synchronous.  Errors: DA_EINVAL (ranges, 0 <= step_begin <=
+ * step_end <= total_steps < 2^31, state not at step_begin), DA_ENOMEM,
+ * DA_EDEVICE. */
+int da_anneal_steps(da_ctx *ctx, const da_schedule *schedule, int64_t replica_base,
+                    int32_t replicas, int64_t total_steps, int64_t step_begin,
+                    int64_t step_end, uint64_t seed, da_result *out);
+
+/* Snapshot layout (host memory, little-endian):
+ *   da_state_header, then for replicas r = 0..R-1 in order: x (N bytes, 0/1),
+ *   best x (N bytes), local fields h = b + W x (N int32, true units), then
+ *   E[R], best E[R], accepted steps[R] (int64 each), E_offset[R] (int32). */
+typedef struct da_state_header {
+    uint32_t magic;            /* 0x54534144 "DAST"                            */
+    uint32_t version;          /* 1                                            */
+    int32_t N;
+    int32_t replicas;
+    int64_t step;              /* steps completed                              */
+    uint64_t replica_base;
+} da_state_header;
+
+/* Bytes of a snapshot of `replicas` replicas of an N-variable instance
+ * (host-only); -1 for bad arguments. */
+int64_t da_state_bytes(int32_t N, int32_t replicas);
+
+/* Copies the first `replicas` replicas of the context's state (as left by the
+ * last da_anneal_steps) to `buf` (host, `bytes` >= da_state_bytes).  Errors:
+ * DA_EINVAL (no state for that many replicas, short buffer), DA_EDEVICE. */
+int da_state_save(da_ctx *ctx, int32_t replicas, void *buf, size_t bytes);
+
+/* Makes a snapshot the context's state, so the next da_anneal_steps may
+ * continue at header.step.  The snapshot must be of an instance with the same
+ * N (the caller is responsible for it being the same instance: fields are
+ * not recomputed).  Errors: DA_EINVAL (bad magic/version, N mismatch, short
+ * buffer), DA_ENOMEM, DA_EDEVICE. */
+int da_state_load(da_ctx *ctx, const void *buf, size_t bytes);
+
 /* Outputs of parallel tempering, indexed by replica id c*M + m (chain c,
  * replica m); any field may be NULL.  slot: temperature index of each replica
  * at the end; n_swaps [chains]: accepted exchanges per chain. */

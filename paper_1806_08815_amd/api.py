@@ -134,6 +134,11 @@ def lib() -> ctypes.CDLL:
         "da_server_destroy": (None, [_P]),
         "da_probe_row_stream": (_i32, [_i32, _i32, _i32, _i32, _i32, _i64,
                                        ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)]),
+        "da_anneal_steps": (_i32, [_P, ctypes.POINTER(da_schedule), _i64, _i32, _i64, _i64, _i64,
+                                   _u64, ctypes.POINTER(da_result)]),
+        "da_state_bytes": (_i64, [_i32, _i32]),
+        "da_state_save": (_i32, [_P, _i32, _P, ctypes.c_size_t]),
+        "da_state_load": (_i32, [_P, _P, ctypes.c_size_t]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -242,6 +247,37 @@ def da_anneal_ex(ctx: Ctx, sched: da_schedule, replica_base: int, replicas: int,
                               ctypes.byref(res), ctypes.byref(tr) if tr is not None else None),
            ctx.ptr)
     return out
+
+
+def da_anneal_steps(ctx: Ctx, sched: da_schedule, replica_base: int, replicas: int,
+                    total_steps: int, step_begin: int, step_end: int, seed: int) -> dict:
+    """Steps [step_begin, step_end) of a total_steps-step anneal (see da.h)."""
+    R = int(replicas)
+    out = _host_outputs(R, ctx.N)
+    res = _result_struct(out)
+    _check(lib().da_anneal_steps(ctx.ptr, ctypes.byref(sched), int(replica_base), R,
+                                 int(total_steps), int(step_begin), int(step_end),
+                                 ctypes.c_uint64(seed), ctypes.byref(res)), ctx.ptr)
+    return out
+
+
+def da_state_bytes(N: int, replicas: int) -> int:
+    return int(lib().da_state_bytes(int(N), int(replicas)))
+
+
+def da_state_save(ctx: Ctx, replicas: int) -> np.ndarray:
+    """Snapshot of the first `replicas` replicas of the context's state (uint8 array)."""
+    n = da_state_bytes(ctx.N, replicas)
+    if n < 0:
+        raise DaError(DA_EINVAL, "bad arguments")
+    buf = np.zeros(n, np.uint8)
+    _check(lib().da_state_save(ctx.ptr, int(replicas), _ptr(buf), n), ctx.ptr)
+    return buf
+
+
+def da_state_load(ctx: Ctx, buf) -> None:
+    b = np.ascontiguousarray(np.asarray(buf, dtype=np.uint8))
+    _check(lib().da_state_load(ctx.ptr, _ptr(b), b.nbytes), ctx.ptr)
 
 
 def device_outputs(R: int, N: int, device="cuda"):

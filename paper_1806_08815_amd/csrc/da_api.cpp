@@ -655,17 +655,26 @@ void record_stats(da_ctx *ctx, const LaunchShape &sh, int64_t launches) {
 }
 
 // Enqueue a full anneal: state init, step kernel between timing events.
+// Steps [step_begin, step_end) of a `steps`-step anneal; step_begin > 0
+// continues from the state the context holds.
 int enqueue_anneal(da_ctx *ctx, const da_schedule *schedule, int64_t replica_base,
                    int32_t replicas, int64_t steps, uint64_t seed, const da_launch *launch,
-                   const da_trace *trace_dev, hipStream_t s, JobDesc &J) {
+                   const da_trace *trace_dev, hipStream_t s, JobDesc &J,
+                   int64_t step_begin = 0, int64_t step_end = -1) {
     std::string err;
     if (!ctx) return fail(nullptr, DA_EINVAL, "ctx is null");
     int rc = validate_schedule(schedule, err);
     if (rc) return fail(ctx, rc, err);
     if (replicas < 1) return fail(ctx, DA_EINVAL, "replicas must be >= 1");
     if (steps < 0 || steps > kMaxSteps) return fail(ctx, DA_EINVAL, "steps must be in [0, 2^31)");
+    if (step_end < 0) step_end = steps;
+    if (step_begin < 0 || step_begin > step_end || step_end > steps)
+        return fail(ctx, DA_EINVAL, "need 0 <= step_begin <= step_end <= total steps");
     if (replica_base < 0 || replica_base + replicas > (int64_t(1) << 31))
         return fail(ctx, DA_EINVAL, "replica ids must lie in [0, 2^31)");
+    if (step_begin > 0 && (ctx->st_step != step_begin || ctx->st_base != replica_base ||
+                           ctx->st_R < replicas))
+        return fail(ctx, DA_EINVAL, "the context holds no state of these replicas at step_begin");
     auto lt = get_level_tables(schedule_temps(*schedule), err);
     if (!lt) return fail(ctx, DA_ENOMEM, err);
     ctx->keep_tables = lt;
@@ -674,14 +683,20 @@ int enqueue_anneal(da_ctx *ctx, const da_schedule *schedule, int64_t replica_bas
                                ? tuned_shape(ctx, *lt, replicas, steps, *schedule, s)
                                : choose_shape(ctx, replicas, launch, true);
     J = make_job(ctx, *lt, replicas, (uint32_t)replica_base, seed, steps, *schedule, sh);
-    rc = init_state(ctx, J, schedule->init, s);
-    if (rc) return rc;
+    J.s0 = step_begin;
+    J.s1 = step_end;
+    // from here on the state changes: it is resumable again only on success
+    ctx->st_step = -1;
+    if (step_begin == 0) {
+        rc = init_state(ctx, J, schedule->init, s);
+        if (rc) return rc;
+    }
     hipEvent_t e0, e1;
     rc = next_events(ctx, e0, e1);
     if (rc) return rc;
     rc = check_hip(ctx, hipEventRecord(e0, s), "event record");
     if (rc) return rc;
-    if (steps > 0) {
+    if (step_end > step_begin) {
         TraceDesc T{nullptr, nullptr, nullptr, steps};
         if (trace_dev) {
             T.k = trace_dev->k;
@@ -696,6 +711,9 @@ int enqueue_anneal(da_ctx *ctx, const da_schedule *schedule, int64_t replica_bas
     rc = check_hip(ctx, hipEventRecord(e1, s), "event record");
     if (rc) return rc;
     record_stats(ctx, sh, 1);
+    ctx->st_step = step_end;
+    ctx->st_base = replica_base;
+    ctx->st_R = replicas;
     return DA_OK;
 }
 
@@ -806,6 +824,104 @@ int da_anneal(da_ctx *ctx, const da_schedule *schedule, int32_t replicas, int64_
     return da_anneal_ex(ctx, schedule, 0, replicas, steps, seed, nullptr, out, nullptr);
 }
 
+int da_anneal_steps(da_ctx *ctx, const da_schedule *schedule, int64_t replica_base,
+                    int32_t replicas, int64_t total_steps, int64_t step_begin,
+                    int64_t step_end, uint64_t seed, da_result *out) {
+    if (!ctx) return fail(nullptr, DA_EINVAL, "ctx is null");
+    hipStream_t s = ctx->own_stream;
+    JobDesc J;
+    int rc = enqueue_anneal(ctx, schedule, replica_base, replicas, total_steps, seed, nullptr,
+                            nullptr, s, J, step_begin, step_end);
+    if (rc) return rc;
+    if (out) return copy_outputs_to_host(ctx, J, replicas, out, s);
+    return check_hip(ctx, hipStreamSynchronize(s), "stream synchronise");
+}
+
+int64_t da_state_bytes(int32_t N, int32_t replicas) {
+    if (N < 1 || N > DA_MAX_N || replicas < 1) return -1;
+    const int64_t n = N, r = replicas;
+    return (int64_t)sizeof(da_state_header) + r * (2 * n + 4 * n) + r * (8 * 3 + 4);
+}
+
+int da_state_save(da_ctx *ctx, int32_t replicas, void *buf, size_t bytes) {
+    if (!ctx || !buf) return fail(ctx, DA_EINVAL, "null argument");
+    if (ctx->st_step < 0 || replicas < 1 || replicas > ctx->st_R)
+        return fail(ctx, DA_EINVAL, "the context holds no anneal state for that many replicas");
+    const int64_t need = da_state_bytes(ctx->N, replicas);
+    if ((int64_t)bytes < need) return fail(ctx, DA_EINVAL, "buffer shorter than da_state_bytes");
+    const size_t N = (size_t)ctx->N, ld = (size_t)ctx->ld, R = (size_t)replicas;
+    auto *hdr = static_cast<da_state_header *>(buf);
+    hdr->magic = 0x54534144u;
+    hdr->version = 1;
+    hdr->N = ctx->N;
+    hdr->replicas = replicas;
+    hdr->step = ctx->st_step;
+    hdr->replica_base = (uint64_t)ctx->st_base;
+    uint8_t *p = static_cast<uint8_t *>(buf) + sizeof(da_state_header);
+    hipStream_t s = ctx->own_stream;
+    uint8_t *x = p, *bx = p + R * N;
+    int32_t *h = reinterpret_cast<int32_t *>(p + 2 * R * N);
+    uint8_t *tail = p + 6 * R * N;
+    hipError_t e = hipMemcpy2DAsync(x, N, ctx->st.x, ld, N, R, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpy2DAsync(bx, N, ctx->st.bx, ld, N, R, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpy2DAsync(h, N * 4, ctx->st.h, ld * 4, N * 4, R, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(tail, ctx->st.E, R * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(tail + R * 8, ctx->st.bE, R * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(tail + R * 16, ctx->st.nacc, R * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(tail + R * 24, ctx->st.eoff, R * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return check_hip(ctx, e, "state copy to host");
+}
+
+int da_state_load(da_ctx *ctx, const void *buf, size_t bytes) {
+    if (!ctx || !buf) return fail(ctx, DA_EINVAL, "null argument");
+    if (bytes < sizeof(da_state_header)) return fail(ctx, DA_EINVAL, "buffer too short");
+    const auto *hdr = static_cast<const da_state_header *>(buf);
+    if (hdr->magic != 0x54534144u || hdr->version != 1)
+        return fail(ctx, DA_EINVAL, "not a version-1 state snapshot");
+    if (hdr->N != ctx->N) return fail(ctx, DA_EINVAL, "snapshot is of a different N");
+    if (hdr->replicas < 1 || hdr->step < 0 || hdr->step > kMaxSteps ||
+        hdr->replica_base + (uint64_t)hdr->replicas > (uint64_t(1) << 31))
+        return fail(ctx, DA_EINVAL, "corrupt snapshot header");
+    const int64_t need = da_state_bytes(hdr->N, hdr->replicas);
+    if ((int64_t)bytes < need) return fail(ctx, DA_EINVAL, "buffer shorter than the snapshot");
+    std::string err;
+    ctx->st_step = -1;
+    if (!ctx->st.ensure(hdr->replicas, ctx->ld, err)) return fail(ctx, DA_ENOMEM, err);
+    const size_t N = (size_t)ctx->N, ld = (size_t)ctx->ld, R = (size_t)hdr->replicas;
+    const uint8_t *p = static_cast<const uint8_t *>(buf) + sizeof(da_state_header);
+    const uint8_t *x = p, *bx = p + R * N, *h = p + 2 * R * N, *tail = p + 6 * R * N;
+    hipStream_t s = ctx->own_stream;
+    // padding columns of the state rows are zero, as the initialisers leave them
+    hipError_t e = hipMemsetAsync(ctx->st.x, 0, R * ld, s);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->st.bx, 0, R * ld, s);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->st.h, 0, R * ld * 4, s);
+    if (e == hipSuccess) e = hipMemcpy2DAsync(ctx->st.x, ld, x, N, N, R, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpy2DAsync(ctx->st.bx, ld, bx, N, N, R, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpy2DAsync(ctx->st.h, ld * 4, h, N * 4, N * 4, R, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ctx->st.E, tail, R * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->st.bE, tail + R * 8, R * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->st.nacc, tail + R * 16, R * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->st.eoff, tail + R * 24, R * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    int rc = check_hip(ctx, e, "state upload");
+    if (rc) return rc;
+    ctx->st_step = hdr->step;
+    ctx->st_base = (int64_t)hdr->replica_base;
+    ctx->st_R = hdr->replicas;
+    return DA_OK;
+}
+
 int da_anneal_batch(const da_batch_item *items, int32_t count, void *stream) {
     if (!items || count < 1) return fail(nullptr, DA_EINVAL, "empty batch");
     hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : nullptr;
@@ -837,6 +953,9 @@ int da_anneal_batch(const da_batch_item *items, int32_t count, void *stream) {
                                    it.steps, it.schedule, sh);
         rc = init_state(ctx, jobs[(size_t)a], it.schedule.init, s);
         if (rc) return rc;
+        ctx->st_step = it.steps;
+        ctx->st_base = it.replica_base;
+        ctx->st_R = it.replicas;
         if (it.steps > 0) append_batch_items(jobs[(size_t)a], a, work);
         record_stats(ctx, sh, 1);
     }
@@ -885,6 +1004,7 @@ int da_pt(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t r
     auto lt = get_level_tables(tv, err);
     if (!lt) return fail(ctx, DA_ENOMEM, err);
     ctx->keep_tables = lt;
+    ctx->st_step = -1;   // PT state is not a resumable anneal
     if (!ctx->st.ensure(R, ctx->ld, err)) return fail(ctx, DA_ENOMEM, err);
     hipStream_t s = ctx->own_stream;
     int rc = DA_OK;

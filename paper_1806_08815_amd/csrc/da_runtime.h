@@ -158,6 +158,11 @@ struct da_ctx {
     double *pt_dbeta = nullptr, *pt_lnU = nullptr;
     int32_t pt_cap_R = 0, pt_cap_M = 0, pt_cap_chains = 0;
     std::shared_ptr<dapt::LevelTables> keep_tables;
+    // what the replica state in `st` holds: replicas st_base .. st_base+st_R-1
+    // after st_step steps (st_step < 0: nothing resumable)
+    int64_t st_step = -1;
+    int64_t st_base = 0;
+    int32_t st_R = 0;
 };
 
 namespace dapt {

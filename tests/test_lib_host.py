@@ -65,3 +65,12 @@ def test_footprint(api):
 def test_strerror(api):
     assert api.da_strerror(api.DA_ENOMEM) == "out of memory"
     assert api.da_strerror(12345) == "unknown status"
+
+
+def test_state_bytes(api):
+    # header (32 bytes) + per replica x, best x (N bytes each), h (4N), E, best E,
+    # accepted count (8 each), offset (4)
+    assert api.da_state_bytes(100, 3) == 32 + 3 * (6 * 100 + 28)
+    assert api.da_state_bytes(8192, 1) == 32 + 6 * 8192 + 28
+    assert api.da_state_bytes(0, 1) == -1 and api.da_state_bytes(10, 0) == -1
+    assert api.da_state_bytes(8193, 1) == -1
