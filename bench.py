@@ -80,15 +80,18 @@ def describe(w):
             f"E_off increment {w.eoff_inc}, {w.init} start, Philox seed {w.seed}")
 
 
-def throughput_leg(api, workloads, name: str, steps=None):
-    """One full anneal of another workload in its autotuned launch (after one
-    warm-up anneal): flip-evals/s, ns per step and row-stream bytes."""
+def throughput_leg(api, workloads, name: str, steps=None, kind=None, n_levels=None):
+    """One full anneal of a workload in its autotuned launch (after one warm-up
+    anneal): flip-evals/s, ns per step and row-stream bytes.  kind / n_levels
+    override the workload's schedule (n_levels = 0: a new temperature every step)."""
     import torch
     w = workloads.WORKLOADS[name]
     Q, _ = w.instance()
     ctx = api.da_create(Q, w.dtype_hint)
     info = ctx.info()
-    sch = api.schedule(w.T_hi, w.T_lo, w.schedule, w.n_levels, w.eoff_inc, w.init)
+    kind = w.schedule if kind is None else kind
+    n_levels = w.n_levels if n_levels is None else n_levels
+    sch = api.schedule(w.T_hi, w.T_lo, kind, n_levels, w.eoff_inc, w.init)
     S = w.steps if steps is None else steps
     out = api.device_outputs(w.replicas, w.N)
     stream = torch.cuda.current_stream()
@@ -104,7 +107,9 @@ def throughput_leg(api, workloads, name: str, steps=None):
     acc = float(out["n_accept"].sum().item())
     row_bytes = acc * w.N * info["dtype"]
     return {
-        "workload": describe(w), "replicas": w.replicas, "mc_steps": S,
+        "workload": describe(w), "schedule": f"{kind}, "
+        + ("a new temperature every step" if n_levels == 0 else f"{n_levels} levels"),
+        "replicas": w.replicas, "mc_steps": S,
         "coupling_storage": f"int{8 * info['dtype']}",
         "flip_evals_per_s": w.replicas * S * w.N / wall,
         "kernel_ms": kern * 1e3, "ns_per_mc_step": kern / S * 1e9,
@@ -461,9 +466,11 @@ def main() -> int:
         result["sk_gaussian_1024"] = throughput_leg(api, workloads, "sk-gaussian-1024")
         result["pt"] = pt_leg(api, workloads, rounds=20)
         result["checkpoint"] = checkpoint_leg(api, workloads, args.workload)
+        result["per_step_schedule"] = throughput_leg(api, workloads, args.workload,
+                                                     kind="linear_beta", n_levels=0)
         print(f"[bench] gaussian and PT legs: {time.perf_counter() - t0:.1f} s; "
               f"{json.dumps(result['sk_gaussian_1024'])} {json.dumps(result['pt'])} "
-              f"{json.dumps(result['checkpoint'])}",
+              f"{json.dumps(result['checkpoint'])} {json.dumps(result['per_step_schedule'])}",
               file=sys.stderr, flush=True)
 
     if not args.skip_extras and args.serve_jobs > 0:

@@ -77,7 +77,11 @@ typedef struct da_ctx da_ctx;
  * T_hi = T_lo = 0 selects a zero-temperature run (only strictly improving
  * flips, d < 0).  eoff_inc >= 0 is the offset_increase_rate of Algorithm 2
  * (0 switches the dynamic offset off, as in the paper's final runs, App. A).
- * 1 <= n_levels <= 4096. */
+ * 1 <= n_levels <= 4096, or n_levels = 0: a new temperature every step, as
+ * in the paper's DA runs (App. A) -- step s runs at level s of an S-level
+ * schedule, S <= 2^24; its flips are decided as d < T_s * (-ln U_u), which
+ * equals the table test d <= thr[u] of that temperature.  Per-step schedules
+ * are run by da_anneal* and da_anneal_batch, not by the server. */
 typedef struct da_schedule {
     double T_hi;
     double T_lo;

@@ -176,19 +176,24 @@ int orc_level_of_step(int64_t s, int L, int64_t S)
     return (int)((s * (int64_t)L) / S);
 }
 
+/* Largest cost d accepted by draw u at temperature T (Sec. III, R4):
+ * ceil(-T ln U_u) - 1 with U_u = (u + 1/2)/65536, clamped to [-1, 2^30]. */
+int32_t orc_thr_entry(double T, uint32_t u)
+{
+    if (!(T > 0.0)) return -1;
+    double U = ((double)u + 0.5) / 65536.0;
+    double y = -T * log(U);
+    double c = ceil(y) - 1.0;
+    int64_t t;
+    if (c >= (double)ORC_THR_MAX) t = ORC_THR_MAX;
+    else t = (int64_t)c;
+    if (t < -1) t = -1;
+    return (int32_t)t;
+}
+
 void orc_threshold_table(double T, int32_t *thr)
 {
-    for (int u = 0; u < 65536; ++u) {
-        if (!(T > 0.0)) { thr[u] = -1; continue; }
-        double U = ((double)u + 0.5) / 65536.0;
-        double y = -T * log(U);
-        double c = ceil(y) - 1.0;
-        int64_t t;
-        if (c >= (double)ORC_THR_MAX) t = ORC_THR_MAX;
-        else t = (int64_t)c;
-        if (t < -1) t = -1;
-        thr[u] = (int32_t)t;
-    }
+    for (int u = 0; u < 65536; ++u) thr[u] = orc_thr_entry(T, (uint32_t)u);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -206,10 +211,11 @@ typedef struct {
 } orc_rep;
 
 /* One Monte Carlo step of replica r at step index s, against the threshold
- * table thr of the temperature in force.  Returns the flipped variable, or -1
- * when no flip was accepted. */
-int orc_step(orc_rep *st, const int64_t *W, const int32_t *thr, uint64_t seed,
-             uint32_t r, uint32_t s, int64_t eoff_inc, uint8_t *acc_scratch)
+ * table thr of the temperature in force, or, when thr is NULL, against the
+ * thresholds of temperature T computed per draw.  Returns the flipped
+ * variable, or -1 when no flip was accepted. */
+int orc_step_T(orc_rep *st, const int64_t *W, const int32_t *thr, double T, uint64_t seed,
+               uint32_t r, uint32_t s, int64_t eoff_inc, uint8_t *acc_scratch)
 {
     const int N = st->N;
     /* Every variable proposes its own flip, tested with dE_j - E_offset. */
@@ -218,7 +224,8 @@ int orc_step(orc_rep *st, const int64_t *W, const int32_t *thr, uint64_t seed,
         int64_t dE = (st->x[i] ? -st->h[i] : st->h[i]);
         int64_t d = dE - st->eoff;
         uint32_t u = orc_metropolis_draw(seed, r, s, (uint32_t)i);
-        acc_scratch[i] = (d <= (int64_t)thr[u]) ? 1 : 0;
+        int32_t t = thr ? thr[u] : orc_thr_entry(T, u);
+        acc_scratch[i] = (d <= (int64_t)t) ? 1 : 0;
         m += acc_scratch[i];
     }
     if (m == 0) {
@@ -253,6 +260,12 @@ int orc_step(orc_rep *st, const int64_t *W, const int32_t *thr, uint64_t seed,
     return k;
 }
 
+int orc_step(orc_rep *st, const int64_t *W, const int32_t *thr, uint64_t seed,
+             uint32_t r, uint32_t s, int64_t eoff_inc, uint8_t *acc_scratch)
+{
+    return orc_step_T(st, W, thr, 0.0, seed, r, s, eoff_inc, acc_scratch);
+}
+
 /* Initial state of replica r: zeros (every run starts from the same state,
  * Algorithm 2; zeros in the paper's runs, App. A) or random bits. */
 enum { ORC_INIT_ZEROS = 0, ORC_INIT_RANDOM = 1 };
@@ -272,7 +285,9 @@ static void orc_init_state(orc_rep *st, const int64_t *W, const int64_t *b,
 }
 
 /* Run R replicas (ids replica_base .. replica_base+R-1) for S steps each
- * through an L-level schedule.  Outputs are [R][N] states and [R] scalars;
+ * through an L-level schedule; L = 0 changes the temperature every step (the
+ * paper's DA runs, App. A): step s runs at level s of an S-level schedule.
+ * Outputs are [R][N] states and [R] scalars;
  * any output pointer may be NULL.  Trace arrays, when given, are [R][S]:
  * the flipped variable (or -1), and E and E_offset after the step.
  * Returns 0, or -1 on bad arguments / allocation failure. */
@@ -283,10 +298,11 @@ int orc_anneal(int N, const int32_t *Q, double T_hi, double T_lo, int kind, int 
                int64_t *n_acc,
                int32_t *trace_k, int64_t *trace_E, int64_t *trace_eoff)
 {
-    if (N < 1 || R < 0 || S < 0 || L < 1) return -1;
+    if (N < 1 || R < 0 || S < 0 || L < 0) return -1;
+    const int per_step = (L == 0);
     int64_t *W = malloc(sizeof(int64_t) * (size_t)N * N);
     int64_t *b = malloc(sizeof(int64_t) * (size_t)N);
-    int32_t *thr = malloc(sizeof(int32_t) * (size_t)L * 65536);
+    int32_t *thr = malloc(sizeof(int32_t) * (size_t)(per_step ? 1 : L) * 65536);
     uint8_t *scratch = malloc((size_t)N);
     orc_rep st;
     st.N = N;
@@ -300,14 +316,24 @@ int orc_anneal(int N, const int32_t *Q, double T_hi, double T_lo, int kind, int 
     orc_derive(N, Q, W, b);
     for (int l = 0; l < L; ++l)
         orc_threshold_table(orc_level_temperature(T_hi, T_lo, kind, L, l), thr + (size_t)l * 65536);
+    if (per_step && S > (int64_t)1 << 30) {
+        free(W); free(b); free(thr); free(scratch); free(st.x); free(st.best_x); free(st.h);
+        return -1;
+    }
 
     for (int rr = 0; rr < R; ++rr) {
         uint32_t r = (uint32_t)(replica_base + rr);
         orc_init_state(&st, W, b, init, seed, r);
         for (int64_t s = 0; s < S; ++s) {
-            int l = orc_level_of_step(s, L, S);
-            int k = orc_step(&st, W, thr + (size_t)l * 65536, seed, r, (uint32_t)s,
-                             eoff_inc, scratch);
+            int k;
+            if (per_step) {
+                double T = orc_level_temperature(T_hi, T_lo, kind, (int)S, (int)s);
+                k = orc_step_T(&st, W, NULL, T, seed, r, (uint32_t)s, eoff_inc, scratch);
+            } else {
+                int l = orc_level_of_step(s, L, S);
+                k = orc_step(&st, W, thr + (size_t)l * 65536, seed, r, (uint32_t)s, eoff_inc,
+                             scratch);
+            }
             if (trace_k) trace_k[(size_t)rr * S + s] = k;
             if (trace_E) trace_E[(size_t)rr * S + s] = st.E;
             if (trace_eoff) trace_eoff[(size_t)rr * S + s] = st.eoff;

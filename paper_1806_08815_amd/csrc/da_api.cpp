@@ -89,8 +89,8 @@ int validate_schedule(const da_schedule *s, std::string &err) {
         err = "unknown schedule kind";
         return DA_EINVAL;
     }
-    if (s->n_levels < 1 || s->n_levels > kMaxLevels) {
-        err = "n_levels must be in [1, 4096]";
+    if (s->n_levels < 0 || s->n_levels > kMaxLevels) {
+        err = "n_levels must be in [0, 4096] (0: a new temperature every step)";
         return DA_EINVAL;
     }
     if (s->eoff_inc < 0) {
@@ -655,6 +655,39 @@ void record_stats(da_ctx *ctx, const LaunchShape &sh, int64_t launches) {
 }
 
 // Enqueue a full anneal: state init, step kernel between timing events.
+// Tables a schedule needs: per-level decision tables, or, for a per-step
+// schedule (n_levels = 0), one dummy level (T = 0, empty band) plus the step
+// table and -ln U_u.
+struct JobTables {
+    std::shared_ptr<LevelTables> levels;
+    std::shared_ptr<StepTables> steps;
+    const double *G = nullptr;
+};
+
+int job_tables(const da_schedule &sch, int64_t steps, JobTables &jt, std::string &err) {
+    if (sch.n_levels == 0) {
+        if (steps > kMaxPerStepSteps) {
+            err = "per-step schedules take at most 2^24 steps";
+            return DA_EINVAL;
+        }
+        jt.levels = get_level_tables(std::vector<double>{0.0}, err);
+        if (!jt.levels) return DA_ENOMEM;
+        if (steps > 0) {
+            jt.steps = get_step_tables(sch, steps, err);
+            jt.G = device_neg_log_u(err);
+            if (!jt.steps || !jt.G) return DA_ENOMEM;
+        }
+        return DA_OK;
+    }
+    jt.levels = get_level_tables(schedule_temps(sch), err);
+    return jt.levels ? DA_OK : DA_ENOMEM;
+}
+
+void attach_step_tables(JobDesc &J, const JobTables &jt) {
+    J.stepT = jt.steps ? jt.steps->d_steps : nullptr;
+    J.G = jt.G;
+}
+
 // Steps [step_begin, step_end) of a `steps`-step anneal; step_begin > 0
 // continues from the state the context holds.
 int enqueue_anneal(da_ctx *ctx, const da_schedule *schedule, int64_t replica_base,
@@ -675,14 +708,19 @@ int enqueue_anneal(da_ctx *ctx, const da_schedule *schedule, int64_t replica_bas
     if (step_begin > 0 && (ctx->st_step != step_begin || ctx->st_base != replica_base ||
                            ctx->st_R < replicas))
         return fail(ctx, DA_EINVAL, "the context holds no state of these replicas at step_begin");
-    auto lt = get_level_tables(schedule_temps(*schedule), err);
-    if (!lt) return fail(ctx, DA_ENOMEM, err);
-    ctx->keep_tables = lt;
+    JobTables jt;
+    rc = job_tables(*schedule, steps, jt, err);
+    if (rc) return fail(ctx, rc, err);
+    ctx->keep_tables = jt.levels;
+    ctx->keep_steps = jt.steps;
     if (!ctx->st.ensure(replicas, ctx->ld, err)) return fail(ctx, DA_ENOMEM, err);
-    const LaunchShape sh = (launch == nullptr && trace_dev == nullptr && tune_enabled())
-                               ? tuned_shape(ctx, *lt, replicas, steps, *schedule, s)
-                               : choose_shape(ctx, replicas, launch, true);
-    J = make_job(ctx, *lt, replicas, (uint32_t)replica_base, seed, steps, *schedule, sh);
+    const LevelTables &lt0 = *jt.levels;
+    const LaunchShape sh =
+        (launch == nullptr && trace_dev == nullptr && tune_enabled() && !jt.steps)
+            ? tuned_shape(ctx, lt0, replicas, steps, *schedule, s)
+            : choose_shape(ctx, replicas, launch, true);
+    J = make_job(ctx, lt0, replicas, (uint32_t)replica_base, seed, steps, *schedule, sh);
+    attach_step_tables(J, jt);
     J.s0 = step_begin;
     J.s1 = step_end;
     // from here on the state changes: it is resumable again only on success
@@ -932,6 +970,7 @@ int da_anneal_batch(const da_batch_item *items, int32_t count, void *stream) {
     std::vector<JobDesc> jobs((size_t)count);
     std::vector<BatchItem> work;
     std::vector<std::shared_ptr<LevelTables>> keep;
+    std::vector<std::shared_ptr<StepTables>> keep_steps;
     for (int32_t a = 0; a < count; ++a) {
         const da_batch_item &it = items[a];
         da_ctx *ctx = it.ctx;
@@ -943,7 +982,11 @@ int da_anneal_batch(const da_batch_item *items, int32_t count, void *stream) {
         if (it.replicas < 1 || it.steps < 0 || it.steps > kMaxSteps || it.replica_base < 0 ||
             it.replica_base + it.replicas > (int64_t(1) << 31))
             return fail(ctx, DA_EINVAL, "bad replicas / steps / replica_base in batch item");
-        auto lt = get_level_tables(schedule_temps(it.schedule), err);
+        JobTables jt;
+        rc = job_tables(it.schedule, it.steps, jt, err);
+        if (rc) return fail(ctx, rc, err);
+        auto lt = jt.levels;
+        if (jt.steps) keep_steps.push_back(jt.steps);
         if (!lt) return fail(ctx, DA_ENOMEM, err);
         keep.push_back(lt);
         ctx->keep_tables = lt;
@@ -951,6 +994,7 @@ int da_anneal_batch(const da_batch_item *items, int32_t count, void *stream) {
         const LaunchShape sh = batch_shape(ctx);
         jobs[(size_t)a] = make_job(ctx, *lt, it.replicas, (uint32_t)it.replica_base, it.seed,
                                    it.steps, it.schedule, sh);
+        attach_step_tables(jobs[(size_t)a], jt);
         rc = init_state(ctx, jobs[(size_t)a], it.schedule.init, s);
         if (rc) return rc;
         ctx->st_step = it.steps;

@@ -39,6 +39,15 @@ constexpr int kMaxN = 8192;
 constexpr int32_t kEoffMax = 1 << 30;
 
 // One anneal segment (or one parallel-tempering round) of one instance.
+// Per-step schedule (temperature changed every step, App. A): the step's
+// temperature and band [tmin, tmax] (= thr[65535], thr[0] at that
+// temperature); an in-band flip is accepted iff d < T * G[u], G[u] = -ln U_u,
+// which equals d <= thr[u] for integer d.
+struct StepT {
+    double T;
+    int32_t tmin, tmax;
+};
+
 struct JobDesc {
     const void *W;
     const int32_t *b;
@@ -66,6 +75,8 @@ struct JobDesc {
     const LevelHdr *hdr;
     const uint32_t *brk;
     const int32_t *thr;
+    const StepT *stepT;          // per-step schedule, else null
+    const double *G;             // -ln U_u, with stepT
 };
 
 struct TraceDesc {

@@ -334,6 +334,9 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         if (!helper) consume(s0, rb);
     }
 
+    StepT st_next{0.0, -1, -1};
+    if (J.stepT && !helper && s0 < s1) st_next = J.stepT[s0];
+
     bool pend = false;   // NW > 1: the previous step's energy change is in dEs
     for (int64_t s = s0; s < s1; ++s) {
         if (s == s_next) {
@@ -343,6 +346,15 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             if (stage) stage_brackets();
         }
         const int par = (int)(s & 1);
+        // per-step schedule: this step's temperature and band (loaded one
+        // step ahead)
+        double Tstep = 0.0;
+        if (J.stepT && !helper) {
+            Tstep = st_next.T;
+            hd.tmin = st_next.tmin;
+            hd.tmax = st_next.tmax;
+            if (s + 1 < s1) st_next = J.stepT[s + 1];
+        }
         int d[F];
         uint32_t acc = 0;
         int c = 0, excl = 0, wtot = 0;
@@ -377,6 +389,21 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                     const int slice = (F >= 8) ? (f & 7) : ((HELP ? 0 : (i0 & 7)) + f);
                     const uint32_t wv = word_of(rb[f >> 3], slice >> 1);
                     u[f] = (slice & 1) ? (wv >> 16) : (wv & 0xFFFFu);
+                }
+                if (J.stepT) {
+                    // per-step schedule: d <= ceil(T G[u]) - 1 <=> d < T G[u]
+                    // (G[u] = -ln U_u; one IEEE product, the threshold's own)
+                    double gv[F];
+#pragma unroll
+                    for (int f = 0; f < F; ++f) gv[f] = J.G[((inb >> f) & 1u) ? u[f] : 0u];
+#pragma unroll
+                    for (int f = 0; f < F; ++f)
+                        acc |= (((inb >> f) & 1u) & (uint32_t)((double)d[f] < Tstep * gv[f]))
+                               << f;
+                    inb = 0;
+                }
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
                     const int bi = ((inb >> f) & 1u) ? ((d[f] - hd.tmin - 1) >> hd.sh) : 0;
                     e[f] = stage ? brk_l[bi] : J.brk[hd.off + bi];
                 }

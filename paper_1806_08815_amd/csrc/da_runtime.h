@@ -30,6 +30,19 @@ struct LevelTables {
 // Threshold table of one temperature (host): thr[u] = ceil(-T ln U_u) - 1,
 // U_u = (u + 1/2) / 65536, clamped to [-1, 2^30]; all -1 for T <= 0.
 void build_threshold_table(double T, int32_t *thr);
+int32_t threshold_entry(double T, int u);
+
+// Per-step schedules: the step table [S] (temperature and band per step) on
+// the device, cached per (device, schedule, S); and -ln U_u [65536] per device.
+struct StepTables {
+    int64_t S = 0;
+    StepT *d_steps = nullptr;
+    size_t bytes = 0;
+    ~StepTables();
+};
+constexpr int64_t kMaxPerStepSteps = int64_t(1) << 24;
+std::shared_ptr<StepTables> get_step_tables(const da_schedule &s, int64_t S, std::string &err);
+const double *device_neg_log_u(std::string &err);
 // Band header and brackets of one level from its threshold table.
 void build_brackets(const int32_t *thr, LevelHdr &hd, std::vector<uint32_t> &brk);
 // Temperature of level l of a schedule.
@@ -158,6 +171,7 @@ struct da_ctx {
     double *pt_dbeta = nullptr, *pt_lnU = nullptr;
     int32_t pt_cap_R = 0, pt_cap_M = 0, pt_cap_chains = 0;
     std::shared_ptr<dapt::LevelTables> keep_tables;
+    std::shared_ptr<dapt::StepTables> keep_steps;
     // what the replica state in `st` holds: replicas st_base .. st_base+st_R-1
     // after st_step steps (st_step < 0: nothing resumable)
     int64_t st_step = -1;

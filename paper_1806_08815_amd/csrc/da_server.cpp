@@ -382,6 +382,8 @@ int da_submit(da_server *srv, const da_job *job, uint64_t *ticket) {
     std::string err;
     int rc = validate_schedule(&job->schedule, err);
     if (rc) return fail(nullptr, rc, err);
+    if (job->schedule.n_levels == 0)
+        return fail(nullptr, DA_EINVAL, "per-step schedules are run by da_anneal*, not served");
     auto j = std::make_unique<Job>();
     rc = derive_storage(job->Q, job->N, job->dtype_hint, j->dtype, j->wscale, err);
     if (rc) return fail(nullptr, rc, err);

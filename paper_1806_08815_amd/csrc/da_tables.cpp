@@ -33,19 +33,17 @@ const double *log_u_table() {
 }
 }  // namespace
 
+int32_t threshold_entry(double T, int u) {
+    if (!(T > 0.0)) return -1;
+    const double y = -T * log_u_table()[u];
+    const double c = std::ceil(y) - 1.0;
+    int64_t t = (c >= (double)kThrMax) ? kThrMax : (int64_t)c;
+    if (t < -1) t = -1;
+    return (int32_t)t;
+}
+
 void build_threshold_table(double T, int32_t *thr) {
-    const double *lnU = log_u_table();
-    for (int u = 0; u < 65536; ++u) {
-        if (!(T > 0.0)) {
-            thr[u] = -1;
-            continue;
-        }
-        const double y = -T * lnU[u];
-        const double c = std::ceil(y) - 1.0;
-        int64_t t = (c >= (double)kThrMax) ? kThrMax : (int64_t)c;
-        if (t < -1) t = -1;
-        thr[u] = (int32_t)t;
-    }
+    for (int u = 0; u < 65536; ++u) thr[u] = threshold_entry(T, u);
 }
 
 // Number of draws accepting cost d: thr is non-increasing in u, so the
@@ -169,6 +167,79 @@ std::shared_ptr<LevelTables> get_level_tables(const std::vector<double> &temps, 
     lt->bytes = thr_b + hdr_b + brk_b;
     g_cache[key] = lt;
     return lt;
+}
+
+StepTables::~StepTables() {
+    if (d_steps) (void)hipFree(d_steps);
+}
+
+namespace {
+std::mutex g_step_mu;
+std::map<std::string, std::weak_ptr<StepTables>> g_step_cache;
+std::mutex g_G_mu;
+std::map<int, double *> g_G;   // per device, held until the process ends
+}  // namespace
+
+std::shared_ptr<StepTables> get_step_tables(const da_schedule &s, int64_t S, std::string &err) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        err = "hipGetDevice failed";
+        return nullptr;
+    }
+    if (S < 1 || S > kMaxPerStepSteps) {
+        err = "per-step schedules take 1 .. 2^24 steps";
+        return nullptr;
+    }
+    std::string key(reinterpret_cast<const char *>(&dev), sizeof dev);
+    key.append(reinterpret_cast<const char *>(&s.T_hi), sizeof s.T_hi);
+    key.append(reinterpret_cast<const char *>(&s.T_lo), sizeof s.T_lo);
+    key.append(reinterpret_cast<const char *>(&s.kind), sizeof s.kind);
+    key.append(reinterpret_cast<const char *>(&S), sizeof S);
+    std::lock_guard<std::mutex> lock(g_step_mu);
+    auto it = g_step_cache.find(key);
+    if (it != g_step_cache.end()) {
+        if (auto sp = it->second.lock()) return sp;
+    }
+    // step s runs at level s of an S-level schedule
+    da_schedule lv = s;
+    lv.n_levels = (int32_t)std::min<int64_t>(S, INT32_MAX);
+    std::vector<StepT> host((size_t)S);
+    for (int64_t q = 0; q < S; ++q) {
+        const double T = schedule_temperature(lv, (int)q);
+        host[(size_t)q] = StepT{T, threshold_entry(T, 65535), threshold_entry(T, 0)};
+    }
+    auto st = std::make_shared<StepTables>();
+    st->S = S;
+    st->bytes = host.size() * sizeof(StepT);
+    if (hipMalloc(&st->d_steps, st->bytes) != hipSuccess ||
+        hipMemcpy(st->d_steps, host.data(), st->bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        err = "per-step table allocation or upload failed";
+        return nullptr;
+    }
+    g_step_cache[key] = st;
+    return st;
+}
+
+const double *device_neg_log_u(std::string &err) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        err = "hipGetDevice failed";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_G_mu);
+    auto it = g_G.find(dev);
+    if (it != g_G.end()) return it->second;
+    std::vector<double> G(65536);
+    const double *lnU = log_u_table();
+    for (int u = 0; u < 65536; ++u) G[(size_t)u] = -lnU[u];
+    double *d = nullptr;
+    if (hipMalloc(&d, G.size() * 8) != hipSuccess ||
+        hipMemcpy(d, G.data(), G.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+        err = "-ln U table allocation or upload failed";
+        return nullptr;
+    }
+    g_G[dev] = d;
+    return d;
 }
 
 }  // namespace dapt

@@ -176,3 +176,53 @@ def test_large_n_trace_parity(api, kind, N, dtype, launch):
     ref = oracle.anneal(Q, T_hi=T_hi, T_lo=T_lo, n_levels=L, eoff_inc=inc, replica_base=1,
                         replicas=R, steps=S, seed=2, trace=True)
     _same(gpu, ref, ("trace_k", "trace_E", "trace_eoff") + KEYS)
+
+
+@pytest.mark.parametrize("rng", [1, -1])
+@pytest.mark.parametrize("kind,N,dtype,F,sk", [
+    ("sk", 64, 0, 4, 0), ("sk", 300, 2, 8, 1), ("gauss", 1024, 0, 4, 1), ("random", 130, 4, 4, 0),
+    ("sk", 1000, 0, 8, 1),
+])
+def test_per_step_schedule_parity(api, kind, N, dtype, F, sk, rng):
+    """A new temperature every step (App. A): thresholds decided as d < T G[u]."""
+    Q = _q(kind, N, 12)
+    if kind == "gauss":
+        T_hi, T_lo, inc = 3.0 * 2**16, 0.05 * 2**16, 2**16
+    elif kind == "random":
+        T_hi, T_lo, inc = 4000.0, 10.0, 50
+    else:
+        T_hi, T_lo, inc = 3.0 * N ** 0.5, 0.1, 1
+    R, S = 4, 900
+    kinds = ("geometric", "linear_beta")
+    ctx = api.da_create(Q, dtype)
+    sch = api.schedule(T_hi, T_lo, kinds[sk], 0, eoff_inc=inc)
+    gpu = api.da_anneal_ex(ctx, sch, 2, R, S, 9, api.launch(F, 1, 0, rng), trace=True)
+    ref = oracle.anneal(Q, T_hi=T_hi, T_lo=T_lo, kind=sk, n_levels=0, eoff_inc=inc,
+                        replica_base=2, replicas=R, steps=S, seed=9, trace=True)
+    _same(gpu, ref, ("trace_k", "trace_E", "trace_eoff") + KEYS)
+
+
+def test_per_step_batch_and_resume(api):
+    import torch
+    Q = _q("sk", 500, 3)
+    sch = api.schedule(60.0, 0.1, "linear_beta", 0, eoff_inc=1)
+    ctx = api.da_create(Q)
+    whole = api.da_anneal_ex(ctx, sch, 0, 6, 2000, 4)
+    ref = oracle.anneal(Q, T_hi=60.0, T_lo=0.1, kind=1, n_levels=0, eoff_inc=1, replicas=6,
+                        steps=2000, seed=4)
+    _same(whole, ref)
+    for a, b in [(0, 700), (700, 701), (701, 2000)]:
+        part = api.da_anneal_steps(ctx, sch, 0, 6, 2000, a, b, 4)
+    _same(part, whole)
+    c2 = api.da_create(Q)
+    item = dict(ctx=c2, schedule=sch, replica_base=0, replicas=6, steps=2000, seed=4,
+                out_dev=api.device_outputs(6, 500))
+    api.da_anneal_batch([item])
+    torch.cuda.synchronize()
+    for k in KEYS:
+        assert np.array_equal(item["out_dev"][k].cpu().numpy(), whole[k]), k
+    srv = api.da_server_create(1 << 30)
+    with pytest.raises(api.DaError) as e:
+        api.da_submit(srv, Q, sch, 6, 2000, 4)
+    assert e.value.code == api.DA_EINVAL
+    srv.close()

@@ -205,3 +205,22 @@ def test_mattis_small_bruteforce(orc):
     Q, c = instances.ising_to_qubo(J)
     e, n, _ = orc.bruteforce(Q)
     assert e + c == -16 * 15 // 2 and n == 2
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_per_step_schedule_is_one_level_per_step(orc, kind):
+    """n_levels = 0 (a new temperature every step, App. A) runs step s at level s of an
+    S-level schedule: the per-draw thresholds give the same run as S level tables."""
+    from paper_1806_08815_amd import instances
+    Q = instances.ising_to_qubo(instances.sk_bimodal(40, 8))[0]
+    S = 300
+    a = orc.anneal(Q, T_hi=12.0, T_lo=0.2, kind=kind, n_levels=0, eoff_inc=1, replicas=3,
+                   steps=S, seed=5, trace=True)
+    b = orc.anneal(Q, T_hi=12.0, T_lo=0.2, kind=kind, n_levels=S, eoff_inc=1, replicas=3,
+                   steps=S, seed=5, trace=True)
+    for k in ("best_x", "best_E", "final_x", "final_E", "n_accept", "trace_k", "trace_E"):
+        assert np.array_equal(a[k], b[k]), k
+    # and it is a different run from a coarse schedule
+    c = orc.anneal(Q, T_hi=12.0, T_lo=0.2, kind=kind, n_levels=4, eoff_inc=1, replicas=3,
+                   steps=S, seed=5, trace=True)
+    assert not np.array_equal(a["trace_k"], c["trace_k"])
