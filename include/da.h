@@ -65,6 +65,13 @@ extern "C" {
 #define DA_INIT_ZEROS 0         /* common all-zero start (Algorithm 2, App. A) */
 #define DA_INIT_RANDOM 1        /* Philox random start, per replica            */
 
+/* Proposals per step (da_schedule.trial). */
+#define DA_TRIAL_PARALLEL 0     /* every variable proposes (Algorithm 2)       */
+#define DA_TRIAL_SINGLE 1       /* variable s mod N alone proposes at step s:
+                                   single-flip Metropolis in sequential sweeps
+                                   (the SA baseline of Sec. III), same tables,
+                                   draws and offset rule                       */
+
 #define DA_MAX_N 8192           /* next-generation DA size (Sec. II.D)         */
 #define DA_EOFF_MAX (1 << 30)   /* saturation of the dynamic offset            */
 
@@ -81,7 +88,8 @@ typedef struct da_ctx da_ctx;
  * in the paper's DA runs (App. A) -- step s runs at level s of an S-level
  * schedule, S <= 2^24; its flips are decided as d < T_s * (-ln U_u), which
  * equals the table test d <= thr[u] of that temperature.  Per-step schedules
- * are run by da_anneal* and da_anneal_batch, not by the server. */
+ * are run by da_anneal* and da_anneal_batch, not by the server.  trial is
+ * DA_TRIAL_PARALLEL (the DA) or DA_TRIAL_SINGLE; reserved must be 0. */
 typedef struct da_schedule {
     double T_hi;
     double T_lo;
@@ -89,6 +97,8 @@ typedef struct da_schedule {
     int32_t n_levels;
     int32_t eoff_inc;
     int32_t init;
+    int32_t trial;
+    int32_t reserved;
 } da_schedule;
 
 /* Outputs of an anneal for R replicas; every field may be NULL (skipped).

@@ -77,7 +77,7 @@ def lib() -> ctypes.CDLL:
         L.orc_threshold_table.argtypes = [dbl, P]
         L.orc_threshold_table.restype = None
         L.orc_anneal.argtypes = [ctypes.c_int, P, dbl, dbl, ctypes.c_int, ctypes.c_int, i64,
-                                 ctypes.c_int, i64, ctypes.c_int, i64, u64,
+                                 ctypes.c_int, ctypes.c_int, i64, ctypes.c_int, i64, u64,
                                  P, P, P, P, P, P, P, P]
         L.orc_anneal.restype = ctypes.c_int
         L.orc_pt.argtypes = [ctypes.c_int, P, P, ctypes.c_int, ctypes.c_int, i64, ctypes.c_int,
@@ -170,8 +170,10 @@ def threshold_table(T: float) -> np.ndarray:
 
 def anneal(Q, *, T_hi: float, T_lo: float, kind: int = SCHED_GEOMETRIC, n_levels: int = 128,
            eoff_inc: int = 0, init: int = INIT_ZEROS, replica_base: int = 0, replicas: int = 1,
-           steps: int = 1000, seed: int = 1, trace: bool = False) -> dict:
-    """Run the oracle DA for `replicas` replicas; returns numpy outputs."""
+           steps: int = 1000, seed: int = 1, trace: bool = False, trial: int = 0) -> dict:
+    """Run the oracle DA for `replicas` replicas; returns numpy outputs.  trial = 1:
+    single-trial Metropolis (variable s mod N proposes at step s) instead of the
+    DA's parallel trial."""
     Q = _q(Q)
     N = Q.shape[0]
     R, S = int(replicas), int(steps)
@@ -186,7 +188,8 @@ def anneal(Q, *, T_hi: float, T_lo: float, kind: int = SCHED_GEOMETRIC, n_levels
         tE = np.zeros((R, S), np.int64)
         to = np.zeros((R, S), np.int64)
     rc = lib().orc_anneal(N, _p(Q), float(T_hi), float(T_lo), int(kind), int(n_levels),
-                          int(eoff_inc), int(init), int(replica_base), R, S, ctypes.c_uint64(seed),
+                          int(eoff_inc), int(init), int(trial), int(replica_base), R, S,
+                          ctypes.c_uint64(seed),
                           _p(out["best_x"]), _p(out["best_E"]), _p(out["final_x"]),
                           _p(out["final_E"]), _p(out["n_accept"]), _p(tk), _p(tE), _p(to))
     if rc != 0:

@@ -212,15 +212,18 @@ typedef struct {
 
 /* One Monte Carlo step of replica r at step index s, against the threshold
  * table thr of the temperature in force, or, when thr is NULL, against the
- * thresholds of temperature T computed per draw.  Returns the flipped
+ * thresholds of temperature T computed per draw.  only < 0: every variable
+ * proposes its flip (the DA's parallel trial, Sec. II.B); only = i: variable i
+ * alone proposes (single-trial Metropolis, Sec. III).  Returns the flipped
  * variable, or -1 when no flip was accepted. */
 int orc_step_T(orc_rep *st, const int64_t *W, const int32_t *thr, double T, uint64_t seed,
-               uint32_t r, uint32_t s, int64_t eoff_inc, uint8_t *acc_scratch)
+               uint32_t r, uint32_t s, int64_t eoff_inc, uint8_t *acc_scratch, int only)
 {
     const int N = st->N;
-    /* Every variable proposes its own flip, tested with dE_j - E_offset. */
+    /* Every proposing variable's flip is tested with dE_j - E_offset. */
     int64_t m = 0;
     for (int i = 0; i < N; ++i) {
+        if (only >= 0 && i != only) { acc_scratch[i] = 0; continue; }
         int64_t dE = (st->x[i] ? -st->h[i] : st->h[i]);
         int64_t d = dE - st->eoff;
         uint32_t u = orc_metropolis_draw(seed, r, s, (uint32_t)i);
@@ -263,7 +266,7 @@ int orc_step_T(orc_rep *st, const int64_t *W, const int32_t *thr, double T, uint
 int orc_step(orc_rep *st, const int64_t *W, const int32_t *thr, uint64_t seed,
              uint32_t r, uint32_t s, int64_t eoff_inc, uint8_t *acc_scratch)
 {
-    return orc_step_T(st, W, thr, 0.0, seed, r, s, eoff_inc, acc_scratch);
+    return orc_step_T(st, W, thr, 0.0, seed, r, s, eoff_inc, acc_scratch, -1);
 }
 
 /* Initial state of replica r: zeros (every run starts from the same state,
@@ -292,7 +295,7 @@ static void orc_init_state(orc_rep *st, const int64_t *W, const int64_t *b,
  * the flipped variable (or -1), and E and E_offset after the step.
  * Returns 0, or -1 on bad arguments / allocation failure. */
 int orc_anneal(int N, const int32_t *Q, double T_hi, double T_lo, int kind, int L,
-               int64_t eoff_inc, int init, int64_t replica_base, int R, int64_t S,
+               int64_t eoff_inc, int init, int trial, int64_t replica_base, int R, int64_t S,
                uint64_t seed,
                uint8_t *best_x, int64_t *best_E, uint8_t *final_x, int64_t *final_E,
                int64_t *n_acc,
@@ -325,14 +328,16 @@ int orc_anneal(int N, const int32_t *Q, double T_hi, double T_lo, int kind, int 
         uint32_t r = (uint32_t)(replica_base + rr);
         orc_init_state(&st, W, b, init, seed, r);
         for (int64_t s = 0; s < S; ++s) {
+            /* single trial: sequential sweeps, variable s mod N at step s */
+            const int only = trial ? (int)(s % N) : -1;
             int k;
             if (per_step) {
                 double T = orc_level_temperature(T_hi, T_lo, kind, (int)S, (int)s);
-                k = orc_step_T(&st, W, NULL, T, seed, r, (uint32_t)s, eoff_inc, scratch);
+                k = orc_step_T(&st, W, NULL, T, seed, r, (uint32_t)s, eoff_inc, scratch, only);
             } else {
                 int l = orc_level_of_step(s, L, S);
-                k = orc_step(&st, W, thr + (size_t)l * 65536, seed, r, (uint32_t)s, eoff_inc,
-                             scratch);
+                k = orc_step_T(&st, W, thr + (size_t)l * 65536, 0.0, seed, r, (uint32_t)s,
+                               eoff_inc, scratch, only);
             }
             if (trace_k) trace_k[(size_t)rr * S + s] = k;
             if (trace_E) trace_E[(size_t)rr * S + s] = st.E;

@@ -1,0 +1,71 @@
+"""Acceptance boost of the parallel trial (Sec. III, Figs. 1-2), measured on the GPU.
+
+For a class of instances at N = 64 and a fixed temperature T, replicas are
+thermalised and then measured in two modes of the same step kernel:
+
+* single trial (one variable proposes per step, sequential sweeps): P_s is the
+  fraction of proposals accepted -- the acceptance probability of standard
+  single-flip Metropolis (Eq. (1));
+* parallel trial (every variable proposes, the DA): P_p is the fraction of
+  steps that accept a flip (Eq. (2)).
+
+Also reported is 1 - (1 - P_s)^N, the value Eq. (2) would give if every
+variable were accepted with the mean single-flip probability independently.
+The instances are the synthetic stand-ins of `instances.py` (SK and 2D torus,
++-1 and Gaussian couplings); temperatures are in Ising units of the
+unquantised couplings, and for +-1 SK in units of sqrt(N) (T_c = 1 for SK).  Run: python -m paper_1806_08815_amd.acceptance
+"""
+from __future__ import annotations
+
+import json
+import sys
+
+import numpy as np
+
+from . import api, instances
+
+CLASSES = {
+    "sk-bimodal": lambda seed: instances.sk_bimodal(64, seed),
+    "sk-gaussian": lambda seed: instances.sk_gaussian(64, seed, scale=2**16),
+    "2d-bimodal": lambda seed: instances.torus2d(8, seed, "bimodal"),
+    "2d-gaussian": lambda seed: instances.torus2d(8, seed, "gaussian", scale=2**16),
+}
+
+
+def acceptance(Q, T: float, trial: str, replicas: int, therm: int, meas: int, seed: int) -> float:
+    ctx = api.da_create(Q)
+    sch = api.schedule(T, T, "geometric", 1, 0, "random", trial)
+    total = therm + meas
+    a = api.da_anneal_steps(ctx, sch, 0, replicas, total, 0, therm, seed)["n_accept"]
+    b = api.da_anneal_steps(ctx, sch, 0, replicas, total, therm, total, seed)["n_accept"]
+    ctx.close()
+    return float((b - a).sum()) / (replicas * meas)
+
+
+def run(temps=None, replicas=512, therm_sweeps=500, meas_sweeps=200, seed=1) -> dict:
+    temps = list(np.geomspace(0.2, 3.0, 10)) if temps is None else temps
+    out = {}
+    for name, make in CLASSES.items():
+        J = make(seed)
+        Q = instances.ising_to_qubo(J)[0]
+        N = Q.shape[0]
+        # Gaussian couplings are quantised at 2^16; +-1 SK couplings are not
+        # normalised by sqrt(N), so their temperature unit is sqrt(N)
+        unit = 2.0**16 if "gaussian" in name else (N ** 0.5 if name.startswith("sk") else 1.0)
+        rows = []
+        for T in temps:
+            ps = acceptance(Q, T * unit, "single", replicas, therm_sweeps * N, meas_sweeps * N,
+                            seed)
+            pp = acceptance(Q, T * unit, "parallel", replicas, therm_sweeps * N,
+                            meas_sweeps * N, seed)
+            rows.append({"T": float(T), "P_s": ps, "P_p": pp,
+                         "independent_trials": 1.0 - (1.0 - ps) ** N,
+                         "boost": pp / ps if ps > 0 else None})
+        out[name] = rows
+    return out
+
+
+if __name__ == "__main__":
+    res = run()
+    json.dump(res, sys.stdout, indent=1)
+    print()

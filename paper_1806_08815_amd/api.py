@@ -20,6 +20,7 @@ DA_OK, DA_EINVAL, DA_ERANGE, DA_ENOMEM, DA_EDEVICE, DA_ENOTREADY, DA_ENOTFOUND =
 DA_DTYPE_AUTO, DA_DTYPE_I8, DA_DTYPE_I16, DA_DTYPE_I32 = 0, 1, 2, 4
 DA_SCHED_GEOMETRIC, DA_SCHED_LINEAR_BETA = 0, 1
 DA_INIT_ZEROS, DA_INIT_RANDOM = 0, 1
+DA_TRIAL_PARALLEL, DA_TRIAL_SINGLE = 0, 1
 
 _P = ctypes.c_void_p
 _i32, _i64, _u64, _dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
@@ -33,7 +34,7 @@ class DaError(RuntimeError):
 
 class da_schedule(ctypes.Structure):
     _fields_ = [("T_hi", _dbl), ("T_lo", _dbl), ("kind", _i32), ("n_levels", _i32),
-                ("eoff_inc", _i32), ("init", _i32)]
+                ("eoff_inc", _i32), ("init", _i32), ("trial", _i32), ("reserved", _i32)]
 
 
 class da_result(ctypes.Structure):
@@ -159,10 +160,13 @@ def _ptr(a: np.ndarray | None):
 
 
 def schedule(T_hi: float, T_lo: float, kind: str | int = "geometric", n_levels: int = 128,
-             eoff_inc: int = 0, init: str | int = "zeros") -> da_schedule:
+             eoff_inc: int = 0, init: str | int = "zeros",
+             trial: str | int = "parallel") -> da_schedule:
     k = {"geometric": DA_SCHED_GEOMETRIC, "linear_beta": DA_SCHED_LINEAR_BETA}.get(kind, kind)
     i = {"zeros": DA_INIT_ZEROS, "random": DA_INIT_RANDOM}.get(init, init)
-    return da_schedule(float(T_hi), float(T_lo), int(k), int(n_levels), int(eoff_inc), int(i))
+    t = {"parallel": DA_TRIAL_PARALLEL, "single": DA_TRIAL_SINGLE}.get(trial, trial)
+    return da_schedule(float(T_hi), float(T_lo), int(k), int(n_levels), int(eoff_inc), int(i),
+                       int(t), 0)
 
 
 def launch(flips_per_lane: int = 0, replicas_per_block: int = 0, w_in_lds: int = 0,

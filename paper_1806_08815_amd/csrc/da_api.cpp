@@ -101,6 +101,10 @@ int validate_schedule(const da_schedule *s, std::string &err) {
         err = "unknown init";
         return DA_EINVAL;
     }
+    if ((s->trial != DA_TRIAL_PARALLEL && s->trial != DA_TRIAL_SINGLE) || s->reserved != 0) {
+        err = "trial must be DA_TRIAL_PARALLEL or DA_TRIAL_SINGLE, reserved 0";
+        return DA_EINVAL;
+    }
     const bool zero = (s->T_hi == 0.0 && s->T_lo == 0.0);
     if (!zero && !(s->T_hi > 0.0 && s->T_lo > 0.0 && std::isfinite(s->T_hi) &&
                    std::isfinite(s->T_lo))) {
@@ -182,6 +186,7 @@ JobDesc make_job(const da_ctx *ctx, const LevelTables &lt, int32_t R, uint32_t r
     J.S = steps;
     J.L = lt.L;
     J.eoff_inc = s.eoff_inc;
+    J.single = s.trial == DA_TRIAL_SINGLE ? 1 : 0;
     J.lvl_of_rep = nullptr;
     J.round_ptr = nullptr;
     J.K = 0;
@@ -1080,7 +1085,8 @@ int da_pt(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t r
     if (!rc) rc = check_hip(ctx, hipMemcpyAsync(ctx->pt_lnU, lnU.data(), 65536 * 8, hipMemcpyHostToDevice, s), "PT upload");
     if (rc) return rc;
 
-    da_schedule sched{temps[0], temps[0], DA_SCHED_GEOMETRIC, 1, eoff_inc, DA_INIT_RANDOM};
+    da_schedule sched{temps[0], temps[0], DA_SCHED_GEOMETRIC, 1, eoff_inc, DA_INIT_RANDOM,
+                      DA_TRIAL_PARALLEL, 0};
     const LaunchShape sh = choose_shape(ctx, R, nullptr, false);
     JobDesc J = make_job(ctx, *lt, R, 0u, seed, 0, sched, sh);
     J.L = M;

@@ -77,6 +77,8 @@ struct JobDesc {
     const int32_t *thr;
     const StepT *stepT;          // per-step schedule, else null
     const double *G;             // -ln U_u, with stepT
+    int32_t single;              // 1: only variable s mod N proposes at step s
+    int32_t pad_;
 };
 
 struct TraceDesc {

@@ -334,6 +334,8 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         if (!helper) consume(s0, rb);
     }
 
+    // single trial: the variable proposing at the current step (s mod N)
+    int prop = J.single ? (int)(s0 % J.N) : 0;
     StepT st_next{0.0, -1, -1};
     if (J.stepT && !helper && s0 < s1) st_next = J.stepT[s0];
 
@@ -362,6 +364,10 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         if (helper) {
             if (s + 1 < s1) produce(s + 1);
         } else {
+            // flips that propose this step: all, or in single-trial mode the
+            // one variable s mod N
+            uint32_t pm = vmask;
+            if (J.single) pm = (g == (prop / F)) ? (vmask & (1u << (prop % F))) : 0u;
             // 1. cost of every flip and the draw-free decisions (branch-free)
             uint32_t inb = 0;
 #pragma unroll
@@ -369,7 +375,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 const int hv = h[f];
                 const int dd = (((xb >> f) & 1u) ? -hv : hv) - eoff;
                 d[f] = dd;
-                const uint32_t v = (vmask >> f) & 1u;
+                const uint32_t v = (pm >> f) & 1u;
                 acc |= (v & (uint32_t)(dd <= hd.tmin)) << f;
                 inb |= (v & (uint32_t)(dd > hd.tmin) & (uint32_t)(dd <= hd.tmax)) << f;
             }
@@ -556,6 +562,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
 #pragma unroll
             for (int q = 0; q < NB; ++q) rb[q] = rbn[q];
         }
+        if (J.single) prop = (prop + 1 == J.N) ? 0 : prop + 1;
         if (TRACE && active && g == 0) {
             T.k[rr * T.stride + (s - s0)] = k;
             T.eoff[rr * T.stride + (s - s0)] = eoff;

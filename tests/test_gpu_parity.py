@@ -226,3 +226,41 @@ def test_per_step_batch_and_resume(api):
         api.da_submit(srv, Q, sch, 6, 2000, 4)
     assert e.value.code == api.DA_EINVAL
     srv.close()
+
+
+@pytest.mark.parametrize("rng", [1, -1])
+@pytest.mark.parametrize("kind,N,dtype,F,L", [
+    ("sk", 64, 0, 4, 16), ("sk", 1000, 2, 8, 16), ("gauss", 513, 0, 4, 8), ("random", 130, 4, 8, 0),
+])
+def test_single_trial_parity(api, kind, N, dtype, F, L, rng):
+    """Single-trial Metropolis in sequential sweeps (the SA baseline, Sec. III) on the
+    same kernels: variable s mod N alone proposes at step s."""
+    Q = _q(kind, N, 14)
+    if kind == "gauss":
+        T_hi, T_lo, inc = 3.0 * 2**16, 0.05 * 2**16, 0
+    elif kind == "random":
+        T_hi, T_lo, inc = 4000.0, 10.0, 0
+    else:
+        T_hi, T_lo, inc = 3.0 * N ** 0.5, 0.1, 0
+    R, S = 3, 2 * N + 37
+    ctx = api.da_create(Q, dtype)
+    sch = api.schedule(T_hi, T_lo, "geometric", L, eoff_inc=inc, init="random", trial="single")
+    gpu = api.da_anneal_ex(ctx, sch, 1, R, S, 6, api.launch(F, 1, 0, rng), trace=True)
+    ref = oracle.anneal(Q, T_hi=T_hi, T_lo=T_lo, n_levels=L, eoff_inc=inc, init=1, trial=1,
+                        replica_base=1, replicas=R, steps=S, seed=6, trace=True)
+    _same(gpu, ref, ("trace_k", "trace_E", "trace_eoff") + KEYS)
+    assert (gpu["trace_k"] >= 0).sum() > 0
+
+
+def test_single_trial_resume_and_serve(api):
+    Q = _q("sk", 300, 8)
+    sch = api.schedule(50.0, 0.5, "geometric", 32, init="random", trial="single")
+    ctx = api.da_create(Q)
+    whole = api.da_anneal_ex(ctx, sch, 0, 5, 3001, 2)
+    api.da_anneal_steps(ctx, sch, 0, 5, 3001, 0, 1111, 2)
+    part = api.da_anneal_steps(ctx, sch, 0, 5, 3001, 1111, 3001, 2)
+    _same(part, whole)
+    srv = api.da_server_create(1 << 30, epoch_steps=700)
+    got = api.da_wait(srv, api.da_submit(srv, Q, sch, 5, 3001, 2))
+    srv.close()
+    _same(got, whole)

@@ -224,3 +224,57 @@ def test_per_step_schedule_is_one_level_per_step(orc, kind):
     c = orc.anneal(Q, T_hi=12.0, T_lo=0.2, kind=kind, n_levels=4, eoff_inc=1, replicas=3,
                    steps=S, seed=5, trace=True)
     assert not np.array_equal(a["trace_k"], c["trace_k"])
+
+
+def test_single_trial_sweeps_in_order(orc):
+    """Single-trial mode: at step s only variable s mod N may flip (sequential sweeps)."""
+    Q = instances.ising_to_qubo(instances.sk_bimodal(30, 4))[0]
+    out = orc.anneal(Q, T_hi=5.0, T_lo=5.0, n_levels=1, replicas=4, steps=600, seed=2,
+                     trace=True, trial=1, init=1)
+    k = out["trace_k"]
+    s = np.arange(600)[None, :].repeat(4, 0)
+    assert np.all((k == -1) | (k == s % 30))
+    assert (k >= 0).sum() > 100
+
+
+def test_single_trial_acceptance_is_metropolis(orc):
+    """One single-trial step from many random states: variable 0 flips with
+    probability min(1, exp(-dE/T)) (Sec. III), dE computed here from Q by numpy."""
+    Q = instances.random_qubo(10, 7, lo=-6, hi=6)
+    N, T, R = 10, 4.0, 40_000
+    out = orc.anneal(Q, T_hi=T, T_lo=T, n_levels=1, replicas=R, steps=1, seed=11, init=1,
+                     trial=1)
+    x0 = np.array([[orc.init_bit(11, r, i) for i in range(N)] for r in range(R)], np.int64)
+    W = Q + Q.T
+    np.fill_diagonal(W, 0)
+    b = np.diag(Q).astype(np.int64)
+    h0 = b[0] + x0 @ W[0].astype(np.int64)
+    dE = (1 - 2 * x0[:, 0]) * h0
+    flipped = out["final_x"][:, 0].astype(np.int64) != x0[:, 0]
+    assert np.all(out["final_x"][:, 1:] == x0[:, 1:])          # nothing else moves
+    for d in np.unique(dE):
+        sel = dE == d
+        n = int(sel.sum())
+        if n < 500:
+            continue
+        p = min(1.0, float(np.exp(-d / T)))
+        f = flipped[sel].mean()
+        tol = 4.5 * np.sqrt(max(p * (1 - p), 1e-4) / n) + 2.0 ** -15
+        assert abs(f - p) < tol, (d, f, p, n)
+
+
+def test_single_trial_zero_temperature_is_greedy_descent(orc):
+    """T = 0, no offset: a variable flips only when that lowers the energy; after
+    enough sweeps the state is a one-flip local minimum (checked with numpy)."""
+    Q = instances.random_qubo(25, 3, lo=-20, hi=20)
+    out = orc.anneal(Q, T_hi=0.0, T_lo=0.0, n_levels=1, replicas=3, steps=25 * 30, seed=1,
+                     init=1, trial=1, trace=True)
+    W = Q + Q.T
+    np.fill_diagonal(W, 0)
+    b = np.diag(Q).astype(np.int64)
+    for r in range(3):
+        x = out["final_x"][r].astype(np.int64)
+        h = b + W.astype(np.int64) @ x
+        assert np.all((1 - 2 * x) * h >= 0)
+        E = out["trace_E"][r]
+        assert np.all(np.diff(E) <= 0)
