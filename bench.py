@@ -468,9 +468,16 @@ def main() -> int:
         result["checkpoint"] = checkpoint_leg(api, workloads, args.workload)
         result["per_step_schedule"] = throughput_leg(api, workloads, args.workload,
                                                      kind="linear_beta", n_levels=0)
+        INT8_PEAK_TOPS = 5000.0
+        fm = {}
+        for n, r in ((1024, 2048), (8192, 8192)):
+            p = api.da_probe_fields_mfma(n, r, 10)
+            fm[f"N{n}_R{r}"] = {**p, "frac_of_int8_peak": p["tera_ops"] / INT8_PEAK_TOPS}
+        result["initial_fields_mfma"] = fm
         print(f"[bench] gaussian and PT legs: {time.perf_counter() - t0:.1f} s; "
               f"{json.dumps(result['sk_gaussian_1024'])} {json.dumps(result['pt'])} "
-              f"{json.dumps(result['checkpoint'])} {json.dumps(result['per_step_schedule'])}",
+              f"{json.dumps(result['checkpoint'])} {json.dumps(result['per_step_schedule'])} "
+              f"{json.dumps(result['initial_fields_mfma'])}",
               file=sys.stderr, flush=True)
 
     if not args.skip_extras and args.serve_jobs > 0:

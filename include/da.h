@@ -339,6 +339,16 @@ int da_probe_row_stream(int32_t n_rows, int32_t row_elems, int32_t dtype_bytes, 
                         int32_t waves_per_chain, int64_t steps, double *ns_per_step,
                         double *gbytes_per_s);
 
+/* Matrix-core probe of the random start's initial fields H = X W^T + b
+ * (Sec. II.D random starts; int8 couplings, v_mfma_i32_32x32x32_i8): times
+ * `iters` launches of the field kernel alone on R random states of a random
+ * +-1 N-variable instance and reports ms per launch and int8 tera-ops/s
+ * (2 ld^2 R per launch, ld = N rounded up to 64).  Allocates and frees its own
+ * device buffers.  Errors: DA_EINVAL (32 <= N <= 8192, R >= 1, iters >= 1),
+ * DA_ENOMEM, DA_EDEVICE. */
+int da_probe_fields_mfma(int32_t N, int32_t R, int32_t iters, double *ms_per_call,
+                         double *tera_ops);
+
 /* ---- continuous-batching server ----------------------------------------- */
 typedef struct da_server da_server;
 

@@ -140,6 +140,8 @@ def lib() -> ctypes.CDLL:
         "da_state_bytes": (_i64, [_i32, _i32]),
         "da_state_save": (_i32, [_P, _i32, _P, ctypes.c_size_t]),
         "da_state_load": (_i32, [_P, _P, ctypes.c_size_t]),
+        "da_probe_fields_mfma": (_i32, [_i32, _i32, _i32, ctypes.POINTER(_dbl),
+                                        ctypes.POINTER(_dbl)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -386,6 +388,14 @@ def da_probe_row_stream(n_rows: int, row_elems: int, dtype_bytes: int, chains: i
                                      int(waves_per_chain), int(steps), ctypes.byref(ns),
                                      ctypes.byref(gbs)))
     return {"ns_per_step": ns.value, "GBps": gbs.value}
+
+
+def da_probe_fields_mfma(N: int, R: int, iters: int) -> dict:
+    ms = _dbl()
+    tops = _dbl()
+    _check(lib().da_probe_fields_mfma(int(N), int(R), int(iters), ctypes.byref(ms),
+                                      ctypes.byref(tops)))
+    return {"ms_per_call": ms.value, "tera_ops": tops.value}
 
 
 # ---- server -----------------------------------------------------------------

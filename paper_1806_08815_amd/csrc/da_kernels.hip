@@ -721,6 +721,90 @@ __global__ __launch_bounds__(256) void k_fields_mfma_i8(const uint8_t *__restric
     }
 }
 
+// Tiled form of the same product for large R x N: a workgroup computes a
+// 128 (replicas) x 128 (variables) block of H with 4 waves of 64 x 64 (2 x 2
+// MFMA tiles each); K advances 64 at a time through LDS (both operands are
+// K-contiguous: rows of X, rows of the symmetric W), so every operand byte
+// read from memory feeds 4 MFMAs.  LDS rows are padded to 80 bytes so the
+// 16-byte fragment reads of 32 consecutive rows spread over the banks.
+constexpr int kFT = 128, kFK = 64, kFRow = kFK + 16;
+
+__global__ __launch_bounds__(256) void k_fields_mfma_i8_tiled(
+    const uint8_t *__restrict__ X, const int8_t *__restrict__ W, const int32_t *__restrict__ b,
+    int32_t *__restrict__ H, int32_t R, int32_t ld, int32_t wscale) {
+    __shared__ __align__(16) int8_t As[kFT * kFRow];
+    __shared__ __align__(16) int8_t Bs[kFT * kFRow];
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wm = wave & 1, wn = wave >> 1;
+    const int r0 = blockIdx.x * kFT, c0 = blockIdx.y * kFT;
+    // staging: thread t copies 32 bytes of row t/2 (k half t&1) of each tile
+    const int srow = t >> 1, sk = (t & 1) * 32;
+    const int ar = min(r0 + srow, R - 1);
+    const bool bvalid = c0 + srow < ld;
+    const int8_t *ga = reinterpret_cast<const int8_t *>(X) + (size_t)ar * ld + sk;
+    const int8_t *gb = W + (size_t)(bvalid ? c0 + srow : 0) * ld + sk;
+    v16i acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0;
+    const int frow = lane & 31, fk = (lane >> 5) * 16;
+    const v4i zero = {0, 0, 0, 0};
+    // the next tile's operands are fetched into registers while this one computes
+    v4i a0 = *reinterpret_cast<const v4i *>(ga);
+    v4i a1 = *reinterpret_cast<const v4i *>(ga + 16);
+    v4i b0 = bvalid ? *reinterpret_cast<const v4i *>(gb) : zero;
+    v4i b1 = bvalid ? *reinterpret_cast<const v4i *>(gb + 16) : zero;
+    for (int k0 = 0; k0 < ld; k0 += kFK) {
+        __syncthreads();   // the previous tile is no longer read
+        *reinterpret_cast<v4i *>(As + srow * kFRow + sk) = a0;
+        *reinterpret_cast<v4i *>(As + srow * kFRow + sk + 16) = a1;
+        *reinterpret_cast<v4i *>(Bs + srow * kFRow + sk) = b0;
+        *reinterpret_cast<v4i *>(Bs + srow * kFRow + sk + 16) = b1;
+        __syncthreads();
+        if (k0 + kFK < ld) {
+            a0 = *reinterpret_cast<const v4i *>(ga + k0 + kFK);
+            a1 = *reinterpret_cast<const v4i *>(ga + k0 + kFK + 16);
+            b0 = bvalid ? *reinterpret_cast<const v4i *>(gb + k0 + kFK) : zero;
+            b1 = bvalid ? *reinterpret_cast<const v4i *>(gb + k0 + kFK + 16) : zero;
+        }
+#pragma unroll
+        for (int kc = 0; kc < kFK; kc += 32) {
+            v4i fa[2], fb[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                fa[i] = *reinterpret_cast<const v4i *>(As + (wm * 64 + i * 32 + frow) * kFRow +
+                                                       kc + fk);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                fb[j] = *reinterpret_cast<const v4i *>(Bs + (wn * 64 + j * 32 + frow) * kFRow +
+                                                       kc + fk);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[i], fb[j], acc[i][j],
+                                                                      0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int col = c0 + wn * 64 + j * 32 + (lane & 31);
+        if (col >= ld) continue;
+        const int bcol = b[col];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int r = r0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                if (r < R) H[(size_t)r * ld + col] = acc[i][j][v] * wscale + bcol;
+            }
+    }
+}
+
 // Initial fields for int16 / int32 couplings: one workgroup per replica adds
 // row j of W for every set bit x_j (rows are coalesced across the workgroup).
 template <typename WT>
@@ -918,7 +1002,12 @@ int launch_rand_bits(uint8_t *X, int32_t R, int32_t N, int32_t ld, uint32_t rid_
 }
 
 int launch_fields(const JobDesc &J, const uint8_t *X, int32_t R, int32_t *H, void *stream) {
-    if (J.dtype == 1) {
+    if (J.dtype == 1 && (int64_t)R * J.ld >= (int64_t)256 * 128 * 128) {
+        // enough 128 x 128 blocks to fill the chip: the LDS-tiled form
+        const dim3 grid((R + kFT - 1) / kFT, (J.ld + kFT - 1) / kFT);
+        hipLaunchKernelGGL(k_fields_mfma_i8_tiled, grid, dim3(256), 0, S(stream), X,
+                           reinterpret_cast<const int8_t *>(J.W), J.b, H, R, J.ld, J.wscale);
+    } else if (J.dtype == 1) {
         const int waves = ((R + 31) / 32) * (J.ld / 32);
         hipLaunchKernelGGL(k_fields_mfma_i8, dim3((waves + 3) / 4), dim3(256), 0, S(stream), X,
                            reinterpret_cast<const int8_t *>(J.W), J.b, H, R, J.ld, J.wscale);

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "da.h"
+#include "da_internal.h"
 
 namespace {
 
@@ -106,6 +107,76 @@ int run_probe(int32_t n_rows, int32_t row_elems, int32_t chains, int32_t waves, 
 }
 
 }  // namespace
+
+// Initial fields of R random states of a random +-1 N-variable instance on the
+// matrix cores (the int8 path of the random start): average time of `iters`
+// launches of the field kernel alone, and int8 ops/s (2 ld^2 R per launch).
+extern "C" int da_probe_fields_mfma(int32_t N, int32_t R, int32_t iters, double *ms_per_call,
+                                    double *tera_ops) {
+    if (N < 32 || N > DA_MAX_N || R < 1 || iters < 1 || !ms_per_call || !tera_ops)
+        return DA_EINVAL;
+    const int32_t ld = (N + 63) / 64 * 64;
+    std::vector<int8_t> w((size_t)ld * ld, 0);
+    std::vector<uint8_t> x((size_t)R * ld, 0);
+    uint64_t st = 0x243F6A8885A308D3ull;
+    auto next = [&]() {
+        st ^= st << 13;
+        st ^= st >> 7;
+        st ^= st << 17;
+        return st;
+    };
+    for (int32_t i = 0; i < N; ++i)
+        for (int32_t j = i + 1; j < N; ++j) {
+            const int8_t v = (next() & 1) ? 1 : -1;
+            w[(size_t)i * ld + j] = v;
+            w[(size_t)j * ld + i] = v;
+        }
+    for (int32_t r = 0; r < R; ++r)
+        for (int32_t i = 0; i < N; ++i) x[(size_t)r * ld + i] = (uint8_t)(next() & 1);
+    int8_t *dW = nullptr;
+    uint8_t *dX = nullptr;
+    int32_t *db = nullptr, *dH = nullptr;
+    int rc = DA_OK;
+    if (hipMalloc(&dW, w.size()) != hipSuccess || hipMalloc(&dX, x.size()) != hipSuccess ||
+        hipMalloc(&db, (size_t)ld * 4) != hipSuccess ||
+        hipMalloc(&dH, (size_t)R * ld * 4) != hipSuccess)
+        rc = DA_ENOMEM;
+    if (!rc && (hipMemcpy(dW, w.data(), w.size(), hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(dX, x.data(), x.size(), hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemset(db, 0, (size_t)ld * 4) != hipSuccess))
+        rc = DA_EDEVICE;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (!rc) {
+        dapt::JobDesc J{};
+        J.W = dW;
+        J.b = db;
+        J.N = N;
+        J.ld = ld;
+        J.dtype = 1;
+        J.wscale = 1;
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+        if (dapt::launch_fields(J, dX, R, dH, nullptr) != 0) rc = DA_EDEVICE;
+        (void)hipEventRecord(a, 0);
+        for (int32_t q = 0; q < iters && !rc; ++q)
+            if (dapt::launch_fields(J, dX, R, dH, nullptr) != 0) rc = DA_EDEVICE;
+        (void)hipEventRecord(b, 0);
+        if (!rc && hipEventSynchronize(b) != hipSuccess) rc = DA_EDEVICE;
+        if (!rc) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, a, b);
+            *ms_per_call = ms / iters;
+            *tera_ops = 2.0 * ld * (double)ld * R / (*ms_per_call * 1e-3) / 1e12;
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+    (void)hipFree(dW);
+    (void)hipFree(dX);
+    (void)hipFree(db);
+    (void)hipFree(dH);
+    return rc;
+}
 
 extern "C" int da_probe_row_stream(int32_t n_rows, int32_t row_elems, int32_t dtype_bytes,
                                    int32_t chains, int32_t waves_per_chain, int64_t steps,

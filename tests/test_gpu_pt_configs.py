@@ -127,3 +127,25 @@ def test_argument_errors(api):
         api.da_pt(ctx, [2.0, 1.0], 1, 1, 1, 0, 1)
     assert e.value.code == api.DA_EINVAL
     assert "ok" in api.da_strerror(0)
+
+
+def test_random_start_tiled_mfma_fields(api):
+    """Random start of many replicas of a +-1 instance: the LDS-tiled int8 MFMA
+    field kernel (R x ld large enough, ragged in both) gives the exact energies of
+    every start state and the oracle's trajectories."""
+    N, R = 1000, 4200
+    Q = instances.ising_to_qubo(instances.sk_bimodal(N, 31))[0]
+    ctx = api.da_create(Q)
+    assert ctx.info()["dtype"] == 1
+    sch = api.schedule(3.0 * N ** 0.5, 0.1, "geometric", 16, 1, "random")
+    g0 = api.da_anneal_ex(ctx, sch, 0, R, 0, 13)
+    X = g0["final_x"].astype(np.int64)
+    Qi = Q.astype(np.int64)
+    E = np.einsum("ri,ij,rj->r", X, Qi, X)
+    assert np.array_equal(g0["final_E"], E)
+    gpu = api.da_anneal_ex(ctx, sch, 0, R, 60, 13)
+    for r in (0, 2047, R - 1):
+        ref = oracle.anneal(Q, T_hi=3.0 * N ** 0.5, T_lo=0.1, n_levels=16, eoff_inc=1, init=1,
+                            replica_base=r, replicas=1, steps=60, seed=13)
+        for k in KEYS:
+            assert np.array_equal(gpu[k][r], ref[k][0]), (r, k)
