@@ -242,7 +242,7 @@ void append_batch_items(const JobDesc &J, int job_index, std::vector<BatchItem> 
 }
 
 int BatchRunner::prepare(std::string &err) {
-    if (exec) return DA_OK;
+    if (exec[0] && exec[1]) return DA_OK;
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -266,24 +266,28 @@ int BatchRunner::prepare(std::string &err) {
     }
     // capture: counter reset (a fill kernel, no memset node) + persistent kernel
     const char *stage = "begin capture";
-    hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        stage = "counter reset node";
-        e = (hipError_t)launch_fill_i32(d_counter, 0, 1, cap_stream);
+    hipError_t e = hipSuccess;
+    for (int v = 0; v < 2 && e == hipSuccess; ++v) {
+        stage = "begin capture";
+        e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            stage = "kernel node";
-            e = (hipError_t)launch_batch(d_jobs, d_items, d_n, d_counter, blocks, 1024, lds,
-                                         cap_stream);
+            stage = "counter reset node";
+            e = (hipError_t)launch_fill_i32(d_counter, 0, 1, cap_stream);
+            if (e == hipSuccess) {
+                stage = "kernel node";
+                e = (hipError_t)launch_batch(d_jobs, d_items, d_n, d_counter, blocks, 1024, lds,
+                                             cap_stream, v == 1);
+            }
+            const hipError_t e2 = hipStreamEndCapture(cap_stream, &graph[v]);
+            if (e == hipSuccess) {
+                stage = "end capture";
+                e = e2;
+            }
         }
-        const hipError_t e2 = hipStreamEndCapture(cap_stream, &graph);
         if (e == hipSuccess) {
-            stage = "end capture";
-            e = e2;
+            stage = "instantiate";
+            e = hipGraphInstantiate(&exec[v], graph[v], nullptr, nullptr, 0);
         }
-    }
-    if (e == hipSuccess) {
-        stage = "instantiate";
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     }
     if (e != hipSuccess) {
         err = std::string("batch graph capture failed at ") + stage + ": " + hipGetErrorString(e);
@@ -301,6 +305,8 @@ int BatchRunner::run(const std::vector<JobDesc> &jobs, const std::vector<BatchIt
         err = "too many jobs in one batch";
         return DA_EINVAL;
     }
+    bool dynamic = false;
+    for (const JobDesc &J : jobs) dynamic = dynamic || J.single || J.stepT;
     // longest items first so the tail of the persistent launch is short
     std::vector<BatchItem> order(items);
     std::stable_sort(order.begin(), order.end(), [&](const BatchItem &p, const BatchItem &q) {
@@ -325,7 +331,7 @@ int BatchRunner::run(const std::vector<JobDesc> &jobs, const std::vector<BatchIt
         if (e == hipSuccess)
             e = hipMemcpyAsync(d_items, h_items, n * sizeof(BatchItem), hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipMemcpyAsync(d_n, h_n, 4, hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipGraphLaunch(exec, s);
+        if (e == hipSuccess) e = hipGraphLaunch(exec[dynamic ? 1 : 0], s);
         if (e != hipSuccess) {
             err = std::string("batch launch failed: ") + hipGetErrorString(e);
             return DA_EDEVICE;
@@ -335,15 +341,17 @@ int BatchRunner::run(const std::vector<JobDesc> &jobs, const std::vector<BatchIt
 }
 
 void BatchRunner::release() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    for (int v = 0; v < 2; ++v) {
+        if (exec[v]) (void)hipGraphExecDestroy(exec[v]);
+        if (graph[v]) (void)hipGraphDestroy(graph[v]);
+        exec[v] = nullptr;
+        graph[v] = nullptr;
+    }
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (void *p : {(void *)d_jobs, (void *)d_items, (void *)d_n, (void *)d_counter})
         if (p) (void)hipFree(p);
     for (void *p : {(void *)h_jobs, (void *)h_items, (void *)h_n})
         if (p) (void)hipHostFree(p);
-    exec = nullptr;
-    graph = nullptr;
     cap_stream = nullptr;
     d_jobs = nullptr;
     d_items = nullptr;

@@ -48,6 +48,9 @@ struct StepT {
     int32_t tmin, tmax;
 };
 
+// Compile-time feature sets of the step kernel (see run_block).
+constexpr int kModePlain = 0, kModeSingle = 1, kModePerStep = 2, kModeDynamic = 4;
+
 struct JobDesc {
     const void *W;
     const int32_t *b;
@@ -107,8 +110,11 @@ int launch_run(const JobDesc &J, int F, bool help, const TraceDesc *trace, int b
                int threads, size_t lds_bytes, void *stream);
 // Persistent batched step kernel; the item count is read from device memory so
 // one captured graph can serve batches of any size.
+// dynamic: the kernel variant that reads each job's optional features
+// (single-trial, per-step schedule) instead of the plain DA step.
 int launch_batch(const JobDesc *jobs_dev, const BatchItem *items_dev, const int32_t *n_items_dev,
-                 int32_t *counter_dev, int blocks, int threads, size_t lds_bytes, void *stream);
+                 int32_t *counter_dev, int blocks, int threads, size_t lds_bytes, void *stream,
+                 bool dynamic);
 int launch_pt_exchange(int64_t *E, int32_t *slot2rep, int32_t *lvl_of_rep, const double *dbeta,
                        const double *lnU, int32_t M, int32_t chains, uint64_t seed,
                        uint32_t *round_ptr, int64_t *n_swaps, void *stream);

@@ -194,9 +194,15 @@ size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk, int
 // buffers (the owning lane writes it after the selection), so it never adds
 // an LDS round trip to the critical path; the energy and the best-state check
 // of step s therefore complete after barrier s+1, before step s+1 flips.
-template <typename WT, int F, bool TRACE, bool HELP, bool STAGE>
+// MODE selects optional features at compile time, so the plain DA step carries
+// none of their code: kModeSingle (single-trial proposals), kModePerStep (a new
+// temperature every step), both, or kModeDynamic (read from the job; used by
+// the batched kernel when a batch mixes them).
+template <typename WT, int F, bool TRACE, bool HELP, bool STAGE, int MODE>
 __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *smem,
                                           const TraceDesc &T) {
+    const bool single = MODE == kModeDynamic ? J.single != 0 : (MODE & kModeSingle) != 0;
+    const bool perstep = MODE == kModeDynamic ? J.stepT != nullptr : (MODE & kModePerStep) != 0;
     static_assert(F == 4 || F == 8, "a lane's record holds at most 8 flips");
     constexpr int NB = (F + 7) / 8;   // Philox blocks per lane
     typedef typename VecOf<WT, F>::type RowV;
@@ -335,9 +341,9 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     }
 
     // single trial: the variable proposing at the current step (s mod N)
-    int prop = J.single ? (int)(s0 % J.N) : 0;
+    int prop = single ? (int)(s0 % J.N) : 0;
     StepT st_next{0.0, -1, -1};
-    if (J.stepT && !helper && s0 < s1) st_next = J.stepT[s0];
+    if (perstep && !helper && s0 < s1) st_next = J.stepT[s0];
 
     bool pend = false;   // NW > 1: the previous step's energy change is in dEs
     for (int64_t s = s0; s < s1; ++s) {
@@ -351,7 +357,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         // per-step schedule: this step's temperature and band (loaded one
         // step ahead)
         double Tstep = 0.0;
-        if (J.stepT && !helper) {
+        if (perstep && !helper) {
             Tstep = st_next.T;
             hd.tmin = st_next.tmin;
             hd.tmax = st_next.tmax;
@@ -364,10 +370,6 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         if (helper) {
             if (s + 1 < s1) produce(s + 1);
         } else {
-            // flips that propose this step: all, or in single-trial mode the
-            // one variable s mod N
-            uint32_t pm = vmask;
-            if (J.single) pm = (g == (prop / F)) ? (vmask & (1u << (prop % F))) : 0u;
             // 1. cost of every flip and the draw-free decisions (branch-free)
             uint32_t inb = 0;
 #pragma unroll
@@ -375,9 +377,15 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 const int hv = h[f];
                 const int dd = (((xb >> f) & 1u) ? -hv : hv) - eoff;
                 d[f] = dd;
-                const uint32_t v = (pm >> f) & 1u;
+                const uint32_t v = (vmask >> f) & 1u;
                 acc |= (v & (uint32_t)(dd <= hd.tmin)) << f;
                 inb |= (v & (uint32_t)(dd > hd.tmin) & (uint32_t)(dd <= hd.tmax)) << f;
+            }
+            // single-trial mode: only variable s mod N proposes this step
+            if (single) {
+                const uint32_t sm = (g == (prop / F)) ? (1u << (prop % F)) : 0u;
+                acc &= sm;
+                inb &= sm;
             }
             // 2. in-band flips: 16-bit draw and bracket.  Every bracket read is
             // issued (out-of-band flips read entry 0) and waited on once; the
@@ -390,13 +398,13 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                                        k0, k1);
                 }
                 uint32_t u[F], e[F];
+                if (perstep) {
 #pragma unroll
-                for (int f = 0; f < F; ++f) {
-                    const int slice = (F >= 8) ? (f & 7) : ((HELP ? 0 : (i0 & 7)) + f);
-                    const uint32_t wv = word_of(rb[f >> 3], slice >> 1);
-                    u[f] = (slice & 1) ? (wv >> 16) : (wv & 0xFFFFu);
-                }
-                if (J.stepT) {
+                    for (int f = 0; f < F; ++f) {
+                        const int slice = (F >= 8) ? (f & 7) : ((HELP ? 0 : (i0 & 7)) + f);
+                        const uint32_t wv = word_of(rb[f >> 3], slice >> 1);
+                        u[f] = (slice & 1) ? (wv >> 16) : (wv & 0xFFFFu);
+                    }
                     // per-step schedule: d <= ceil(T G[u]) - 1 <=> d < T G[u]
                     // (G[u] = -ln U_u; one IEEE product, the threshold's own)
                     double gv[F];
@@ -410,6 +418,9 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 }
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
+                    const int slice = (F >= 8) ? (f & 7) : ((HELP ? 0 : (i0 & 7)) + f);
+                    const uint32_t wv = word_of(rb[f >> 3], slice >> 1);
+                    u[f] = (slice & 1) ? (wv >> 16) : (wv & 0xFFFFu);
                     const int bi = ((inb >> f) & 1u) ? ((d[f] - hd.tmin - 1) >> hd.sh) : 0;
                     e[f] = stage ? brk_l[bi] : J.brk[hd.off + bi];
                 }
@@ -562,7 +573,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
 #pragma unroll
             for (int q = 0; q < NB; ++q) rb[q] = rbn[q];
         }
-        if (J.single) prop = (prop + 1 == J.N) ? 0 : prop + 1;
+        if (single) prop = (prop + 1 == J.N) ? 0 : prop + 1;
         if (TRACE && active && g == 0) {
             T.k[rr * T.stride + (s - s0)] = k;
             T.eoff[rr * T.stride + (s - s0)] = eoff;
@@ -608,16 +619,16 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     }
 }
 
-template <typename WT, int F, bool TRACE, bool HELP, bool STAGE>
+template <typename WT, int F, bool TRACE, bool HELP, bool STAGE, int MODE>
 __global__ __launch_bounds__(1024) void k_run(JobDesc J, TraceDesc T) {
     extern __shared__ __align__(16) uint8_t smem[];
-    run_block<WT, F, TRACE, HELP, STAGE>(J, blockIdx.x, smem, T);
+    run_block<WT, F, TRACE, HELP, STAGE, MODE>(J, blockIdx.x, smem, T);
 }
 
 // Persistent batched form: workgroups pull (job, replica-block) items from a
 // device counter until none are left.  Every item of a launch uses the
 // launch's workgroup size; jobs of any size and coupling type mix freely.
-template <int F>
+template <int F, int MODE>
 __global__ __launch_bounds__(1024) void k_batch(const JobDesc *__restrict__ jobs,
                                                 const BatchItem *__restrict__ items,
                                                 const int32_t *n_items_ptr, int32_t *counter) {
@@ -634,9 +645,9 @@ __global__ __launch_bounds__(1024) void k_batch(const JobDesc *__restrict__ jobs
         const BatchItem bi = items[it];
         JobDesc J = jobs[bi.job];
         const int blk = bi.r0 / J.RPW;
-        if (J.dtype == 1) run_block<int8_t, F, false, false, true>(J, blk, smem, T);
-        else if (J.dtype == 2) run_block<int16_t, F, false, false, true>(J, blk, smem, T);
-        else run_block<int32_t, F, false, false, true>(J, blk, smem, T);
+        if (J.dtype == 1) run_block<int8_t, F, false, false, true, MODE>(J, blk, smem, T);
+        else if (J.dtype == 2) run_block<int16_t, F, false, false, true, MODE>(J, blk, smem, T);
+        else run_block<int32_t, F, false, false, true, MODE>(J, blk, smem, T);
         __syncthreads();
     }
 }
@@ -939,12 +950,31 @@ inline int grid_for(int64_t n, int threads) {
 template <typename WT, int F, bool TRACE, bool HELP>
 int launch_run_t(const JobDesc &J, const TraceDesc &T, int blocks, int threads, size_t lds,
                  void *stream) {
-    if (J.lvl_of_rep)
-        hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, false>), dim3(blocks), dim3(threads), lds,
-                           S(stream), J, T);
-    else
-        hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true>), dim3(blocks), dim3(threads), lds,
-                           S(stream), J, T);
+    const dim3 g(blocks), b(threads);
+    if (J.lvl_of_rep) {
+        hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, false, kModePlain>), g, b, lds, S(stream),
+                           J, T);
+        return (int)hipGetLastError();
+    }
+    const int mode = (J.single ? kModeSingle : 0) | (J.stepT ? kModePerStep : 0);
+    switch (mode) {
+        case kModePlain:
+            hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, kModePlain>), g, b, lds,
+                               S(stream), J, T);
+            break;
+        case kModeSingle:
+            hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, kModeSingle>), g, b, lds,
+                               S(stream), J, T);
+            break;
+        case kModePerStep:
+            hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, kModePerStep>), g, b, lds,
+                               S(stream), J, T);
+            break;
+        default:
+            hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, kModeSingle | kModePerStep>), g,
+                               b, lds, S(stream), J, T);
+            break;
+    }
     return (int)hipGetLastError();
 }
 
@@ -982,9 +1012,14 @@ int launch_run(const JobDesc &J, int F, bool help, const TraceDesc *trace, int b
 }
 
 int launch_batch(const JobDesc *jobs_dev, const BatchItem *items_dev, const int32_t *n_items_dev,
-                 int32_t *counter_dev, int blocks, int threads, size_t lds_bytes, void *stream) {
-    hipLaunchKernelGGL((k_batch<8>), dim3(blocks), dim3(threads), lds_bytes, S(stream), jobs_dev,
-                       items_dev, n_items_dev, counter_dev);
+                 int32_t *counter_dev, int blocks, int threads, size_t lds_bytes, void *stream,
+                 bool dynamic) {
+    if (dynamic)
+        hipLaunchKernelGGL((k_batch<8, kModeDynamic>), dim3(blocks), dim3(threads), lds_bytes,
+                           S(stream), jobs_dev, items_dev, n_items_dev, counter_dev);
+    else
+        hipLaunchKernelGGL((k_batch<8, kModePlain>), dim3(blocks), dim3(threads), lds_bytes,
+                           S(stream), jobs_dev, items_dev, n_items_dev, counter_dev);
     return (int)hipGetLastError();
 }
 

@@ -109,8 +109,9 @@ struct BatchRunner {
     int blocks = 0;
     size_t lds = 0;
     hipStream_t cap_stream = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // [0]: plain DA step kernel; [1]: the variant reading per-job features
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
     int prepare(std::string &err);
     // Enqueues the batch on `s` (jobs must already have initialised state).
     int run(const std::vector<JobDesc> &jobs, const std::vector<BatchItem> &items, hipStream_t s,
