@@ -164,15 +164,28 @@ typedef struct da_info {
     int32_t dtype;             /* bytes per stored coupling (1, 2, 4)        */
     int32_t wscale;            /* W = wscale * stored W (common factor)      */
     int64_t device_bytes;      /* device memory held by the context now     */
+    int32_t sparse_degree;     /* entries per row of the sparse copy, 0: none */
+    int32_t reserved;
 } da_info;
+
+/* OR-ed into da_create's dtype_hint: besides dense W, keep every row's
+ * nonzero couplings as a padded list (the row's largest degree D, rounded up
+ * to a multiple of 4, of 32-bit entries column | (W_ij / wscale) << 16), and
+ * run anneals on it: an accepted step then reads D entries of row k (from LDS
+ * when the list fits there) instead of the whole dense row, and updates only
+ * the fields of k's neighbours.  Needs |W_ij / wscale| <= 32767 and D <= 1024;
+ * results are identical to the dense path.  Parallel tempering uses the
+ * dense copy. */
+#define DA_STORE_SPARSE 0x100
 
 /* Build a context for E(x) = x^T Q x.  Q is N x N int32, row-major, host;
  * it is copied (the caller keeps its buffer).  Derives W and b (Sec. V),
  * takes out the greatest common divisor of W as wscale, stores W/wscale in
  * dtype_hint (or the smallest exact type for DA_DTYPE_AUTO) and uploads W and
- * b to the current HIP device.  Errors: DA_EINVAL (null, N < 1, N > DA_MAX_N,
- * bad hint), DA_ERANGE (max_i |b_i| + sum_j |W_ij| > 2^30, or W/wscale does
- * not fit the forced type), DA_ENOMEM, DA_EDEVICE (no gfx950 device). */
+ * b to the current HIP device; with DA_STORE_SPARSE also the sparse row lists.
+ * Errors: DA_EINVAL (null, N < 1, N > DA_MAX_N, bad hint), DA_ERANGE
+ * (max_i |b_i| + sum_j |W_ij| > 2^30, W/wscale does not fit the forced type,
+ * or a sparse list out of range), DA_ENOMEM, DA_EDEVICE (no gfx950 device). */
 int da_create(const int32_t *Q, int32_t N, int32_t dtype_hint, da_ctx **out);
 
 /* Frees the context and its device memory; NULL is a no-op. */

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libdapt.so")
 DA_OK, DA_EINVAL, DA_ERANGE, DA_ENOMEM, DA_EDEVICE, DA_ENOTREADY, DA_ENOTFOUND = (
     0, -1, -2, -3, -4, -5, -6)
 DA_DTYPE_AUTO, DA_DTYPE_I8, DA_DTYPE_I16, DA_DTYPE_I32 = 0, 1, 2, 4
+DA_STORE_SPARSE = 0x100
 DA_SCHED_GEOMETRIC, DA_SCHED_LINEAR_BETA = 0, 1
 DA_INIT_ZEROS, DA_INIT_RANDOM = 0, 1
 DA_TRIAL_PARALLEL, DA_TRIAL_SINGLE = 0, 1
@@ -60,7 +61,7 @@ class da_kernel_stats(ctypes.Structure):
 
 class da_info(ctypes.Structure):
     _fields_ = [("N", _i32), ("ld", _i32), ("dtype", _i32), ("wscale", _i32),
-                ("device_bytes", _i64)]
+                ("device_bytes", _i64), ("sparse_degree", _i32), ("reserved", _i32)]
 
 
 class da_batch_item(ctypes.Structure):

@@ -149,7 +149,10 @@ LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch,
     rpw = std::max(1, std::min(rpw, 16 / per));
     rpw = std::min(rpw, std::max(R, 1));
     sh.RPW = rpw;
-    const int64_t w_bytes = (int64_t)ctx->N * ctx->ld * ctx->dtype;
+    // what an anneal may stage in LDS: the sparse lists, else dense W
+    const int64_t w_bytes = (anneal_mode && ctx->ell_D > 0)
+                                ? (int64_t)ctx->N * ctx->ell_D * 4
+                                : (int64_t)ctx->N * ctx->ld * ctx->dtype;
     const int want = launch ? launch->w_in_lds : 0;
     sh.w_lds = (want >= 0 && w_bytes <= (want > 0 ? device_lds_limit() : 32 * 1024)) ? 1 : 0;
     sh.threads = 64 * per * sh.RPW;
@@ -187,6 +190,8 @@ JobDesc make_job(const da_ctx *ctx, const LevelTables &lt, int32_t R, uint32_t r
     J.L = lt.L;
     J.eoff_inc = s.eoff_inc;
     J.single = s.trial == DA_TRIAL_SINGLE ? 1 : 0;
+    J.ell = ctx->d_ell;
+    J.ell_D = ctx->ell_D;
     J.lvl_of_rep = nullptr;
     J.round_ptr = nullptr;
     J.K = 0;
@@ -306,7 +311,7 @@ int BatchRunner::run(const std::vector<JobDesc> &jobs, const std::vector<BatchIt
         return DA_EINVAL;
     }
     bool dynamic = false;
-    for (const JobDesc &J : jobs) dynamic = dynamic || J.single || J.stepT;
+    for (const JobDesc &J : jobs) dynamic = dynamic || J.single || J.stepT || J.ell;
     // longest items first so the tail of the persistent launch is short
     std::vector<BatchItem> order(items);
     std::stable_sort(order.begin(), order.end(), [&](const BatchItem &p, const BatchItem &q) {
@@ -438,6 +443,34 @@ void prepare_matrix(const int32_t *Q, int32_t N, int32_t dtype, int32_t wscale, 
     for (size_t i = 0; i < n; ++i) hm.b[i] = Q[i * n + i];
 }
 
+int prepare_sparse(const int32_t *Q, int32_t N, HostMatrix &hm, std::string &err) {
+    const size_t n = (size_t)N;
+    const int64_t g = hm.wscale;
+    std::vector<std::vector<uint32_t>> rows(n);
+    for (size_t i = 0; i < n; ++i)
+        for (size_t j = 0; j < n; ++j) {
+            if (i == j) continue;
+            const int64_t w = ((int64_t)Q[i * n + j] + (int64_t)Q[j * n + i]) / g;
+            if (!w) continue;
+            if (w < -32768 || w > 32767) {
+                err = "a coupling does not fit the 16-bit sparse entry";
+                return DA_ERANGE;
+            }
+            rows[i].push_back((uint32_t)j | ((uint32_t)(uint16_t)(int16_t)w << 16));
+        }
+    size_t D = 4;
+    for (auto &r : rows) D = std::max(D, (r.size() + 3) / 4 * 4);
+    if (D > 1024) {
+        err = "a row has more than 1024 nonzeros: use dense storage";
+        return DA_ERANGE;
+    }
+    hm.ell_D = (int32_t)D;
+    hm.ell.assign(n * D, 0xFFFFu);   // padding: column 0xFFFF, value 0
+    for (size_t i = 0; i < n; ++i)
+        std::copy(rows[i].begin(), rows[i].end(), hm.ell.begin() + (ptrdiff_t)(i * D));
+    return DA_OK;
+}
+
 int create_ctx(const HostMatrix &hm, hipStream_t s, da_ctx **out, std::string &err) {
     da_ctx *ctx = new (std::nothrow) da_ctx();
     if (!ctx) {
@@ -459,6 +492,13 @@ int create_ctx(const HostMatrix &hm, hipStream_t s, da_ctx **out, std::string &e
     if (!what && (e = hipMemcpyAsync(ctx->d_b, hm.b.data(), hm.b.size() * 4,
                                      hipMemcpyHostToDevice, s)) != hipSuccess)
         what = "b upload";
+    if (!what && hm.ell_D > 0) {
+        ctx->ell_D = hm.ell_D;
+        if ((e = hipMalloc(&ctx->d_ell, hm.ell.size() * 4)) != hipSuccess) what = "sparse allocation";
+        else if ((e = hipMemcpyAsync(ctx->d_ell, hm.ell.data(), hm.ell.size() * 4,
+                                     hipMemcpyHostToDevice, s)) != hipSuccess)
+            what = "sparse upload";
+    }
     // the host image may be freed when this returns
     if (!what && (e = hipStreamSynchronize(s)) != hipSuccess) what = "upload";
     if (!what && (e = hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking)) !=
@@ -777,6 +817,8 @@ int da_create(const int32_t *Q, int32_t N, int32_t dtype_hint, da_ctx **out) {
     *out = nullptr;
     if (!Q) return fail(nullptr, DA_EINVAL, "Q is null");
     if (N < 1 || N > DA_MAX_N) return fail(nullptr, DA_EINVAL, "N must be in [1, 8192]");
+    const bool sparse = (dtype_hint & DA_STORE_SPARSE) != 0;
+    dtype_hint &= ~DA_STORE_SPARSE;
     if (dtype_hint != DA_DTYPE_AUTO && dtype_hint != DA_DTYPE_I8 && dtype_hint != DA_DTYPE_I16 &&
         dtype_hint != DA_DTYPE_I32)
         return fail(nullptr, DA_EINVAL, "unknown dtype hint");
@@ -788,6 +830,10 @@ int da_create(const int32_t *Q, int32_t N, int32_t dtype_hint, da_ctx **out) {
     if (rc) return fail(nullptr, rc, err);
     HostMatrix hm;
     prepare_matrix(Q, N, dtype, wscale, hm);
+    if (sparse) {
+        rc = prepare_sparse(Q, N, hm, err);
+        if (rc) return fail(nullptr, rc, err);
+    }
     rc = create_ctx(hm, nullptr, out, err);
     if (rc) return fail(nullptr, rc, err);
     return DA_OK;
@@ -800,6 +846,7 @@ void da_destroy(da_ctx *ctx) {
     ctx->st.release();
     if (ctx->d_W) (void)hipFree(ctx->d_W);
     if (ctx->d_b) (void)hipFree(ctx->d_b);
+    if (ctx->d_ell) (void)hipFree(ctx->d_ell);
     for (void *p : {(void *)ctx->pt_slot2rep, (void *)ctx->pt_lvl, (void *)ctx->pt_swaps,
                     (void *)ctx->pt_round, (void *)ctx->pt_dbeta, (void *)ctx->pt_lnU})
         if (p) (void)hipFree(p);
@@ -818,7 +865,9 @@ int da_get_info(const da_ctx *ctx, da_info *info) {
     info->dtype = ctx->dtype;
     info->wscale = ctx->wscale;
     info->device_bytes = (int64_t)ctx->ld * ctx->ld * ctx->dtype + (int64_t)ctx->ld * 4 +
-                         ctx->st.bytes();
+                         ctx->st.bytes() + (int64_t)ctx->N * ctx->ell_D * 4;
+    info->sparse_degree = ctx->ell_D;
+    info->reserved = 0;
     return DA_OK;
 }
 

@@ -49,7 +49,8 @@ struct StepT {
 };
 
 // Compile-time feature sets of the step kernel (see run_block).
-constexpr int kModePlain = 0, kModeSingle = 1, kModePerStep = 2, kModeDynamic = 4;
+constexpr int kModePlain = 0, kModeSingle = 1, kModePerStep = 2, kModeDynamic = 4,
+              kModeSparse = 8;
 
 struct JobDesc {
     const void *W;
@@ -81,7 +82,8 @@ struct JobDesc {
     const StepT *stepT;          // per-step schedule, else null
     const double *G;             // -ln U_u, with stepT
     int32_t single;              // 1: only variable s mod N proposes at step s
-    int32_t pad_;
+    int32_t ell_D;               // sparse row lists: entries per row (0: dense)
+    const uint32_t *ell;         // [N][ell_D] column | value << 16, or null
 };
 
 struct TraceDesc {

@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "da_internal.h"
 
@@ -203,6 +204,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                                           const TraceDesc &T) {
     const bool single = MODE == kModeDynamic ? J.single != 0 : (MODE & kModeSingle) != 0;
     const bool perstep = MODE == kModeDynamic ? J.stepT != nullptr : (MODE & kModePerStep) != 0;
+    const bool sparse = MODE == kModeDynamic ? J.ell != nullptr : (MODE & kModeSparse) != 0;
     static_assert(F == 4 || F == 8, "a lane's record holds at most 8 flips");
     constexpr int NB = (F + 7) / 8;   // Philox blocks per lane
     typedef typename VecOf<WT, F>::type RowV;
@@ -241,7 +243,9 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     }
 
     // --- LDS carve-up: [W][brackets][per replica slot] -----------------------
-    const int w_bytes = J.w_lds ? ((J.N * ld * (int)sizeof(WT) + 15) & ~15) : 0;
+    // LDS may hold dense W, or with sparse rows the row lists instead
+    const int w_src = sparse ? J.N * J.ell_D * 4 : J.N * ld * (int)sizeof(WT);
+    const int w_bytes = J.w_lds ? ((w_src + 15) & ~15) : 0;
     const WT *Wl = reinterpret_cast<const WT *>(smem);
     uint32_t *brk_l = reinterpret_cast<uint32_t *>(smem + w_bytes);
     const SlotLayout SL = slot_layout(NW, NH);
@@ -253,9 +257,9 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     uint4 *draws = reinterpret_cast<uint4 *>(sel + SL.draws);      // [2][NH*64] Philox blocks
 
     if (J.w_lds) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(J.W);
+        const uint4 *src = reinterpret_cast<const uint4 *>(sparse ? (const void *)J.ell : J.W);
         uint4 *dst = reinterpret_cast<uint4 *>(smem);
-        const int n16 = (J.N * ld * (int)sizeof(WT)) / 16;
+        const int n16 = w_src / 16;
         for (int q = threadIdx.x; q < n16; q += blockDim.x) dst[q] = src[q];
         __syncthreads();
     }
@@ -520,7 +524,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         // 4. fetch row k of W (the step's only bulk traffic), then, while it
         // is in flight, finish the previous step's energy and best state
         RowV raw;
-        if (m > 0) {
+        if (m > 0 && !sparse) {
             // address-space-typed loads: a generic pointer would make this one
             // flat load that waits on both the vector and the LDS counters
             typedef __attribute__((address_space(3))) const RowV LdsRowV;
@@ -548,7 +552,48 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 dEs[par] = dsel + eoff;
             }
             xb ^= owner ? (1u << (k % F)) : 0u;
-            if (wscale == 1) {
+            if (sparse) {
+                // only k's neighbours change: walk its row list (entries are
+                // uniform; the owning wave's owning lane adds)
+                constexpr int lF = F == 8 ? 3 : 2;
+                const int dw = delta * wscale;
+                const uint32_t *er = (J.w_lds ? reinterpret_cast<const uint32_t *>(smem) : J.ell) +
+                                     (size_t)k * J.ell_D;
+                bool more = true;
+                for (int q = 0; q < J.ell_D && more; q += 4) {
+                    typedef uint32_t U4 __attribute__((ext_vector_type(4)));
+                    U4 e4;
+                    if (J.w_lds) e4 = *(__attribute__((address_space(3))) const U4 *)(er + q);
+                    else e4 = *reinterpret_cast<const U4 *>(er + q);
+                    const uint32_t ev[4] = {
+                        (uint32_t)__builtin_amdgcn_readfirstlane((int)e4[0]),
+                        (uint32_t)__builtin_amdgcn_readfirstlane((int)e4[1]),
+                        (uint32_t)__builtin_amdgcn_readfirstlane((int)e4[2]),
+                        (uint32_t)__builtin_amdgcn_readfirstlane((int)e4[3])};
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const int col = (int)(ev[c] & 0xFFFFu);
+                        if (col == 0xFFFF) {
+                            more = false;
+                            break;
+                        }
+                        const int gl = col >> lF;
+                        if ((gl >> 6) == wr && lane == (gl & 63)) {
+                            const int add = ((int)ev[c] >> 16) * dw;
+                            switch (col & (F - 1)) {
+                                case 0: h[0] += add; break;
+                                case 1: h[1] += add; break;
+                                case 2: h[2] += add; break;
+                                case 3: h[3] += add; break;
+                                case 4: h[F > 4 ? 4 : 0] += add; break;
+                                case 5: h[F > 5 ? 5 : 0] += add; break;
+                                case 6: h[F > 6 ? 6 : 0] += add; break;
+                                default: h[F > 7 ? 7 : 0] += add; break;
+                            }
+                        }
+                    }
+                }
+            } else if (wscale == 1) {
 #pragma unroll
                 for (int f = 0; f < F; ++f) h[f] += delta > 0 ? (int)raw[f] : -(int)raw[f];
             } else {
@@ -957,6 +1002,35 @@ int launch_run_t(const JobDesc &J, const TraceDesc &T, int blocks, int threads, 
         return (int)hipGetLastError();
     }
     const int mode = (J.single ? kModeSingle : 0) | (J.stepT ? kModePerStep : 0);
+    if (J.ell) {
+        // sparse row lists: the coupling type of dense W plays no part, so
+        // these variants exist once (launch_run routes sparse jobs here)
+        if constexpr (std::is_same<WT, int16_t>::value) {
+            constexpr int SP = kModeSparse;
+            switch (mode) {
+                case kModePlain:
+                    hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, SP>), g, b, lds,
+                                       S(stream), J, T);
+                    break;
+                case kModeSingle:
+                    hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, SP | kModeSingle>), g, b,
+                                       lds, S(stream), J, T);
+                    break;
+                case kModePerStep:
+                    hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, SP | kModePerStep>), g, b,
+                                       lds, S(stream), J, T);
+                    break;
+                default:
+                    hipLaunchKernelGGL(
+                        (k_run<WT, F, TRACE, HELP, true, SP | kModeSingle | kModePerStep>), g, b,
+                        lds, S(stream), J, T);
+                    break;
+            }
+            return (int)hipGetLastError();
+        } else {
+            return (int)hipErrorInvalidValue;
+        }
+    }
     switch (mode) {
         case kModePlain:
             hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, kModePlain>), g, b, lds,
@@ -1003,6 +1077,8 @@ int launch_run_w(const JobDesc &J, int F, bool help, const TraceDesc *trace, int
 
 int launch_run(const JobDesc &J, int F, bool help, const TraceDesc *trace, int blocks,
                int threads, size_t lds_bytes, void *stream) {
+    if (J.ell && !J.lvl_of_rep)
+        return launch_run_w<int16_t>(J, F, help, trace, blocks, threads, lds_bytes, stream);
     switch (J.dtype) {
         case 1: return launch_run_w<int8_t>(J, F, help, trace, blocks, threads, lds_bytes, stream);
         case 2: return launch_run_w<int16_t>(J, F, help, trace, blocks, threads, lds_bytes, stream);

@@ -138,7 +138,12 @@ struct HostMatrix {
     int32_t N = 0, ld = 0, dtype = 0, wscale = 1;
     std::vector<uint8_t> W;
     std::vector<int32_t> b;
+    int32_t ell_D = 0;             // sparse row lists: D entries per row, 0 = none
+    std::vector<uint32_t> ell;     // [N][D] column | (W_ij / wscale) << 16
 };
+// Adds the sparse row lists to hm; DA_ERANGE (err set) when a value does not
+// fit 16 bits or a row has more than 1024 nonzeros.
+int prepare_sparse(const int32_t *Q, int32_t N, HostMatrix &hm, std::string &err);
 // Fills hm for a storage choice made by derive_storage.
 void prepare_matrix(const int32_t *Q, int32_t N, int32_t dtype, int32_t wscale, HostMatrix &hm);
 // New context holding hm on the current device (uploaded on stream s, which
@@ -155,6 +160,8 @@ struct da_ctx {
     int device = 0;
     void *d_W = nullptr;
     int32_t *d_b = nullptr;
+    uint32_t *d_ell = nullptr;   // sparse row lists [N][ell_D], or null
+    int32_t ell_D = 0;
     dapt::StateBuf st;
     hipStream_t own_stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;          // last call

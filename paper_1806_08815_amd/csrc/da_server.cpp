@@ -4,8 +4,8 @@
 //   * host preparation (two prep threads): the device image of the coupling
 //     matrix and the host image of the level tables of each submitted job;
 //   * admission (the device worker): prepared jobs are admitted first-fit, in
-//     submission order, while their device footprint (da_job_footprint) fits
-//     the free budget; an admitted job's matrix, tables and initial state are
+//     submission order (never ahead of an earlier job still being prepared),
+//     while their device footprint (da_job_footprint) fits the free budget; an admitted job's matrix, tables and initial state are
 //     uploaded on an upload stream while the current epoch runs;
 //   * epochs: every resident job advances by up to epoch_steps Monte Carlo
 //     steps, all of them together in one persistent launch of the batched
@@ -94,6 +94,17 @@ struct da_server {
     int start_job(Job &j);
     void retire(std::unique_ptr<Job> &j);
     bool known_locked(uint64_t ticket) const;
+    uint64_t first_unprepared_locked() const {
+        uint64_t t = UINT64_MAX;
+        for (auto &q : incoming) t = std::min(t, q->ticket);
+        for (uint64_t p : preparing) t = std::min(t, p);
+        return t;
+    }
+    // something the device worker can do now
+    bool has_work_locked() const {
+        return stop || !resident.empty() ||
+               (!queue.empty() && queue.front()->ticket < first_unprepared_locked());
+    }
 };
 
 extern "C" int64_t da_job_footprint(int32_t N, int32_t dtype_bytes, int32_t replicas,
@@ -161,7 +172,10 @@ int da_server::start_job(Job &j) {
 
 bool da_server::admit_locked(std::vector<Job *> &admitted) {
     bool any = false;
+    // submission order: a job never overtakes an earlier one still being prepared
+    const uint64_t first_unprepared = first_unprepared_locked();
     for (auto it = queue.begin(); it != queue.end();) {
+        if ((*it)->ticket > first_unprepared) break;
         if (max_resident > 0 && (int32_t)(resident.size() + admitted.size()) >= max_resident) break;
         if ((*it)->footprint <= (int64_t)budget - used) {
             used += (*it)->footprint;
@@ -221,8 +235,7 @@ void da_server::run() {
         std::vector<Job *> admitted;
         {
             std::unique_lock<std::mutex> lock(mu);
-            if (!inflight)
-                cv_work.wait(lock, [&] { return stop || !queue.empty() || !resident.empty(); });
+            if (!inflight) cv_work.wait(lock, [&] { return has_work_locked(); });
             if (stop) {
                 for (auto *dq : {&incoming, &queue})
                     for (auto &q : *dq) {
@@ -385,7 +398,9 @@ int da_submit(da_server *srv, const da_job *job, uint64_t *ticket) {
     if (job->schedule.n_levels == 0)
         return fail(nullptr, DA_EINVAL, "per-step schedules are run by da_anneal*, not served");
     auto j = std::make_unique<Job>();
-    rc = derive_storage(job->Q, job->N, job->dtype_hint, j->dtype, j->wscale, err);
+    // the server keeps jobs in dense storage (sparse row lists are a da_create option)
+    rc = derive_storage(job->Q, job->N, job->dtype_hint & ~DA_STORE_SPARSE, j->dtype, j->wscale,
+                        err);
     if (rc) return fail(nullptr, rc, err);
     j->footprint = da_job_footprint(job->N, j->dtype, job->replicas, job->schedule.n_levels);
     if (j->footprint > (int64_t)srv->budget)
