@@ -145,6 +145,48 @@ def pt_leg(api, workloads, rounds: int):
     }
 
 
+def sparse_sweep_leg(api, R=128, S=20_000):
+    """Step time of dense rows vs sparse row lists over coupling density (the
+    paper's density study, Sec. VI.C, at N = 1024), and on a large 2D torus."""
+    import torch
+    from paper_1806_08815_amd import instances
+    cases = [("torus L=32", instances.torus2d(32, 1, "bimodal"))]
+    for p in (0.01, 0.02, 0.05, 0.1, 0.2, 0.5):
+        cases.append((f"G(1024, {p})", instances.erdos_renyi(1024, p, 1)))
+    cases.append(("torus L=90 (N=8100)", instances.torus2d(90, 1, "bimodal")))
+    out = []
+    stream = torch.cuda.current_stream()
+    for name, J in cases:
+        Q = instances.ising_to_qubo(J)[0]
+        N = Q.shape[0]
+        deg = float((J != 0).sum(axis=1).mean())
+        T_hi = 3.0 * max(1.0, deg ** 0.5)
+        sch = api.schedule(T_hi, 0.05 * T_hi, "geometric", 128, 1)
+        row = {"instance": name, "N": N, "mean_degree": deg}
+        for label, hint in (("dense", 0), ("sparse", api.DA_STORE_SPARSE)):
+            try:
+                ctx = api.da_create(Q, hint)
+            except api.DaError as e:
+                row[label] = str(e)
+                continue
+            o = api.device_outputs(R, N)
+            api.da_anneal_async(ctx, sch, 0, R, S, 1, None, o, stream)
+            torch.cuda.synchronize()
+            api.da_reset_kernel_stats(ctx)
+            api.da_anneal_async(ctx, sch, 0, R, S, 1, None, o, stream)
+            torch.cuda.synchronize()
+            ks = api.da_last_kernel_stats(ctx)
+            row[label] = {"ns_per_step": ks["kernel_ms"] / S * 1e6,
+                          "row_list_in_lds": bool(ks["w_in_lds"]) if label == "sparse" else None,
+                          "degree_slots": ctx.info()["sparse_degree"]}
+            row.setdefault("same_results", []).append(o["best_E"].cpu().numpy().tolist())
+            ctx.close()
+        same = row.pop("same_results", [])
+        row["sparse_equals_dense"] = len(same) == 2 and same[0] == same[1]
+        out.append(row)
+    return out
+
+
 def checkpoint_leg(api, workloads, name: str, cut_frac: float = 0.5):
     """Stop the workload's anneal part-way, snapshot it to host memory, resume in a
     fresh context, and compare with the uninterrupted run."""
@@ -474,10 +516,11 @@ def main() -> int:
             p = api.da_probe_fields_mfma(n, r, 10)
             fm[f"N{n}_R{r}"] = {**p, "frac_of_int8_peak": p["tera_ops"] / INT8_PEAK_TOPS}
         result["initial_fields_mfma"] = fm
+        result["sparse_rows"] = sparse_sweep_leg(api)
         print(f"[bench] gaussian and PT legs: {time.perf_counter() - t0:.1f} s; "
               f"{json.dumps(result['sk_gaussian_1024'])} {json.dumps(result['pt'])} "
               f"{json.dumps(result['checkpoint'])} {json.dumps(result['per_step_schedule'])} "
-              f"{json.dumps(result['initial_fields_mfma'])}",
+              f"{json.dumps(result['initial_fields_mfma'])} {json.dumps(result['sparse_rows'])}",
               file=sys.stderr, flush=True)
 
     if not args.skip_extras and args.serve_jobs > 0:

@@ -154,13 +154,17 @@ LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch,
                                 ? (int64_t)ctx->N * ctx->ell_D * 4
                                 : (int64_t)ctx->N * ctx->ld * ctx->dtype;
     const int want = launch ? launch->w_in_lds : 0;
-    sh.w_lds = (want >= 0 && w_bytes <= (want > 0 ? device_lds_limit() : 32 * 1024)) ? 1 : 0;
+    const bool sparse = anneal_mode && ctx->ell_D > 0;
+    // dense W goes to LDS automatically only when small; row lists whenever they fit
+    sh.w_lds = (want >= 0 && w_bytes <= ((want > 0 || sparse) ? device_lds_limit() : 32 * 1024))
+                   ? 1
+                   : 0;
     sh.threads = 64 * per * sh.RPW;
     sh.blocks = (R + sh.RPW - 1) / sh.RPW;
-    sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, sh.w_lds ? (int)w_bytes : 0, stage, sh.NH);
+    sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, sh.w_lds ? (int)w_bytes : 0, stage, sh.NH, sparse);
     if (sh.lds > (size_t)device_lds_limit() && sh.w_lds) {
         sh.w_lds = 0;
-        sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0, stage, sh.NH);
+        sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0, stage, sh.NH, sparse);
     }
     return sh;
 }
@@ -238,7 +242,7 @@ LaunchShape batch_shape(const da_ctx *ctx) {
     sh.RPW = 16 / sh.NW;
     sh.w_lds = 0;
     sh.threads = 1024;
-    sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0, 1, 0);
+    sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0, 1, 0, ctx->ell_D > 0);
     return sh;
 }
 
@@ -253,7 +257,9 @@ int BatchRunner::prepare(std::string &err) {
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     blocks = cus;
     lds = 0;
-    for (int nw = 1; nw <= 16; ++nw) lds = std::max(lds, run_lds_bytes(nw, 16 / nw, 8, 0, 1, 0));
+    // room for any job, sparse row lists' delta buffers included
+    for (int nw = 1; nw <= 16; ++nw)
+        lds = std::max(lds, run_lds_bytes(nw, 16 / nw, 8, 0, 1, 0, true));
     if (hipMalloc(&d_jobs, sizeof(JobDesc) * kCapJobs) != hipSuccess ||
         hipMalloc(&d_items, sizeof(BatchItem) * kCapItems) != hipSuccess ||
         hipMalloc(&d_n, 4) != hipSuccess || hipMalloc(&d_counter, 4) != hipSuccess ||

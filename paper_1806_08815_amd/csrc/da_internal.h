@@ -133,12 +133,13 @@ int device_lds_limit();
 // LDS of one replica slot of a workgroup (byte offsets): the selection
 // exchange of multi-wave replicas (wave totals, lane records, the energy
 // hand-off) and, with random-number waves, the selection-draw ring and the
-// double-buffered Philox blocks.
+// double-buffered Philox blocks; with sparse row lists (dhF = flips per lane)
+// one field-delta buffer of 64 * dhF int32 per compute wave.
 struct SlotLayout {
-    int tot, rec, dEs, vring, draws, bytes;
+    int tot, rec, dEs, vring, draws, dh, bytes;
 };
-__host__ __device__ inline SlotLayout slot_layout(int NW, int NH) {
-    SlotLayout L{0, 0, 0, 0, 0, 0};
+__host__ __device__ inline SlotLayout slot_layout(int NW, int NH, int dhF = 0) {
+    SlotLayout L{0, 0, 0, 0, 0, 0, 0};
     int off = 0;
     if (NW > 1 || NH > 0) {
         L.tot = off;
@@ -155,12 +156,18 @@ __host__ __device__ inline SlotLayout slot_layout(int NW, int NH) {
         L.draws = off;
         off += 2 * NH * 64 * 16;
     }
+    if (dhF > 0) {
+        off = (off + 15) & ~15;
+        L.dh = off;
+        off += NW * 64 * dhF * 4;
+    }
     L.bytes = (off + 15) & ~15;
     return L;
 }
 
 // Workgroup LDS bytes the run kernel needs for a launch shape (stage_brk: the
 // level's bracket table is staged in LDS, anneal mode).
-size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk, int NH);
+size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk, int NH,
+                     bool sparse = false);
 
 }  // namespace dapt

@@ -165,9 +165,9 @@ __device__ __forceinline__ int row16_incl_scan(int v) {
 
 }  // namespace
 
-size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk, int NH) {
-    (void)F;
-    const SlotLayout SL = slot_layout(NW, NH);
+size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk, int NH,
+                     bool sparse) {
+    const SlotLayout SL = slot_layout(NW, NH, sparse ? F : 0);
     size_t w = (size_t)((w_lds_bytes + 15) & ~15);
     size_t b = stage_brk ? (size_t)kMaxBuckets * 4 : 0;
     return w + b + (size_t)SL.bytes * RPW;
@@ -248,13 +248,19 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     const int w_bytes = J.w_lds ? ((w_src + 15) & ~15) : 0;
     const WT *Wl = reinterpret_cast<const WT *>(smem);
     uint32_t *brk_l = reinterpret_cast<uint32_t *>(smem + w_bytes);
-    const SlotLayout SL = slot_layout(NW, NH);
+    const SlotLayout SL = slot_layout(NW, NH, sparse ? F : 0);
     uint8_t *sel = smem + w_bytes + (stage ? kMaxBuckets * 4 : 0) + (size_t)SL.bytes * slot;
     int *tot = reinterpret_cast<int *>(sel + SL.tot);              // [2][NW]
     uint32_t *rec = reinterpret_cast<uint32_t *>(sel + SL.rec);    // [2][NW*64]
     int *dEs = reinterpret_cast<int *>(sel + SL.dEs);              // [2]
     uint32_t *vring = reinterpret_cast<uint32_t *>(sel + SL.vring);  // [4] selection draws
     uint4 *draws = reinterpret_cast<uint4 *>(sel + SL.draws);      // [2][NH*64] Philox blocks
+    // sparse rows: this wave's field-delta buffer [64 * F], kept all zero between steps
+    int *dh = reinterpret_cast<int *>(sel + SL.dh) + (helper ? 0 : wr) * 64 * F;
+    if (sparse && !helper) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) dh[lane * F + f] = 0;
+    }
 
     if (J.w_lds) {
         const uint4 *src = reinterpret_cast<const uint4 *>(sparse ? (const void *)J.ell : J.W);
@@ -553,46 +559,30 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             }
             xb ^= owner ? (1u << (k % F)) : 0u;
             if (sparse) {
-                // only k's neighbours change: walk its row list (entries are
-                // uniform; the owning wave's owning lane adds)
-                constexpr int lF = F == 8 ? 3 : 2;
+                // only k's neighbours change.  Each wave takes the entries of
+                // row k's list that fall in its own columns: one lane per
+                // entry scatters the value into the wave's delta buffer, every
+                // lane reads its F slots and clears them.  LDS operations of
+                // one wave complete in order, so no barrier.
                 const int dw = delta * wscale;
                 const uint32_t *er = (J.w_lds ? reinterpret_cast<const uint32_t *>(smem) : J.ell) +
                                      (size_t)k * J.ell_D;
-                bool more = true;
-                for (int q = 0; q < J.ell_D && more; q += 4) {
-                    typedef uint32_t U4 __attribute__((ext_vector_type(4)));
-                    U4 e4;
-                    if (J.w_lds) e4 = *(__attribute__((address_space(3))) const U4 *)(er + q);
-                    else e4 = *reinterpret_cast<const U4 *>(er + q);
-                    const uint32_t ev[4] = {
-                        (uint32_t)__builtin_amdgcn_readfirstlane((int)e4[0]),
-                        (uint32_t)__builtin_amdgcn_readfirstlane((int)e4[1]),
-                        (uint32_t)__builtin_amdgcn_readfirstlane((int)e4[2]),
-                        (uint32_t)__builtin_amdgcn_readfirstlane((int)e4[3])};
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        const int col = (int)(ev[c] & 0xFFFFu);
-                        if (col == 0xFFFF) {
-                            more = false;
-                            break;
-                        }
-                        const int gl = col >> lF;
-                        if ((gl >> 6) == wr && lane == (gl & 63)) {
-                            const int add = ((int)ev[c] >> 16) * dw;
-                            switch (col & (F - 1)) {
-                                case 0: h[0] += add; break;
-                                case 1: h[1] += add; break;
-                                case 2: h[2] += add; break;
-                                case 3: h[3] += add; break;
-                                case 4: h[F > 4 ? 4 : 0] += add; break;
-                                case 5: h[F > 5 ? 5 : 0] += add; break;
-                                case 6: h[F > 6 ? 6 : 0] += add; break;
-                                default: h[F > 7 ? 7 : 0] += add; break;
-                            }
-                        }
-                    }
+                const int base = wr * 64 * F;
+                for (int q0 = 0; q0 < J.ell_D; q0 += 64) {
+                    const int j = min(q0 + lane, J.ell_D - 1);
+                    const uint32_t e = J.w_lds ? *(__attribute__((address_space(3))) const uint32_t *)(er + j)
+                                               : er[j];
+                    const int c = (int)(e & 0xFFFFu) - base;
+                    if (q0 + lane < J.ell_D && (unsigned)c < (unsigned)(64 * F))
+                        dh[c] = (int)e >> 16;
                 }
+                int dv[F];
+#pragma unroll
+                for (int f = 0; f < F; ++f) dv[f] = dh[lane * F + f];
+#pragma unroll
+                for (int f = 0; f < F; ++f) h[f] += dv[f] * dw;
+#pragma unroll
+                for (int f = 0; f < F; ++f) dh[lane * F + f] = 0;
             } else if (wscale == 1) {
 #pragma unroll
                 for (int f = 0; f < F; ++f) h[f] += delta > 0 ? (int)raw[f] : -(int)raw[f];
