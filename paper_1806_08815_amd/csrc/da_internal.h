@@ -50,7 +50,7 @@ struct StepT {
 
 // Compile-time feature sets of the step kernel (see run_block).
 constexpr int kModePlain = 0, kModeSingle = 1, kModePerStep = 2, kModeDynamic = 4,
-              kModeSparse = 8;
+              kModeSparse = 8, kModeWide = 16;
 
 struct JobDesc {
     const void *W;

@@ -198,7 +198,9 @@ size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk, int
 // MODE selects optional features at compile time, so the plain DA step carries
 // none of their code: kModeSingle (single-trial proposals), kModePerStep (a new
 // temperature every step), both, or kModeDynamic (read from the job; used by
-// the batched kernel when a batch mixes them).
+// the batched kernel when a batch mixes them).  kModeWide states that every
+// replica spans several compute waves and W is read from global memory, so
+// the single-wave and LDS-resident paths drop out of the step loop.
 template <typename WT, int F, bool TRACE, bool HELP, bool STAGE, int MODE>
 __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *smem,
                                           const TraceDesc &T) {
@@ -211,7 +213,9 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     const int lane = threadIdx.x & 63;
     // wave-level quantities are uniform: keep them in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int NW = J.NW;
+    constexpr bool wide = (MODE & kModeWide) != 0;
+    const int NW = wide ? max(J.NW, 2) : J.NW;
+    const int w_lds = wide ? 0 : J.w_lds;
     const int NH = HELP ? J.NH : 0;
     const int ncomp = J.RPW * NW;
     const bool helper = HELP && wave >= ncomp;
@@ -231,6 +235,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     const uint32_t k1 = (uint32_t)(J.seed >> 32);
     const int ld = J.ld;
     const int wscale = J.wscale;
+    const bool mul24 = sizeof(WT) < 4 && wscale < (1 << 23) && wscale > -(1 << 23);
     constexpr bool stage = STAGE;
     const bool sync = HELP || NW > 1;       // a workgroup barrier every step
     const int nblk = (J.N + 7) >> 3;        // Philox blocks per replica-step
@@ -245,7 +250,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     // --- LDS carve-up: [W][brackets][per replica slot] -----------------------
     // LDS may hold dense W, or with sparse rows the row lists instead
     const int w_src = sparse ? J.N * J.ell_D * 4 : J.N * ld * (int)sizeof(WT);
-    const int w_bytes = J.w_lds ? ((w_src + 15) & ~15) : 0;
+    const int w_bytes = w_lds ? ((w_src + 15) & ~15) : 0;
     const WT *Wl = reinterpret_cast<const WT *>(smem);
     uint32_t *brk_l = reinterpret_cast<uint32_t *>(smem + w_bytes);
     const SlotLayout SL = slot_layout(NW, NH, sparse ? F : 0);
@@ -262,7 +267,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         for (int f = 0; f < F; ++f) dh[lane * F + f] = 0;
     }
 
-    if (J.w_lds) {
+    if (w_lds) {
         const uint4 *src = reinterpret_cast<const uint4 *>(sparse ? (const void *)J.ell : J.W);
         uint4 *dst = reinterpret_cast<uint4 *>(smem);
         const int n16 = w_src / 16;
@@ -356,10 +361,15 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     if (perstep && !helper && s0 < s1) st_next = J.stepT[s0];
 
     bool pend = false;   // NW > 1: the previous step's energy change is in dEs
-    for (int64_t s = s0; s < s1; ++s) {
-        if (s == s_next) {
+    // countdowns (steps left, steps to the next level) tested for equality
+    // only: 64-bit equality is a scalar compare, ordering is not
+    int64_t to_next = s_next - s0;
+    int64_t s = s0;
+    for (int64_t left = s1 > s0 ? s1 - s0 : 0; left != 0; --left, ++s, --to_next) {
+        if (to_next == 0) {
             lvl = level_of(s, J.L, J.S);
             s_next = next_level_step(lvl, J.L, J.S);
+            to_next = s_next - s;
             hd = J.hdr[lvl];
             if (stage) stage_brackets();
         }
@@ -371,14 +381,14 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             Tstep = st_next.T;
             hd.tmin = st_next.tmin;
             hd.tmax = st_next.tmax;
-            if (s + 1 < s1) st_next = J.stepT[s + 1];
+            if (left != 1) st_next = J.stepT[s + 1];
         }
         int d[F];
         uint32_t acc = 0;
         int c = 0, excl = 0, wtot = 0;
 
         if (helper) {
-            if (s + 1 < s1) produce(s + 1);
+            if (left != 1) produce(s + 1);
         } else {
             // 1. cost of every flip and the draw-free decisions (branch-free)
             uint32_t inb = 0;
@@ -468,7 +478,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         // in one straight-line group (clamped indices, no branches), so the
         // wave waits for LDS once.
         uint4 rbn[NB];
-        if (HELP) consume(s + 1 < s1 ? s + 1 : s, rbn);
+        if (HELP) consume(left != 1 ? s + 1 : s, rbn);
         const uint32_t vs = HELP ? vring[(int)(s & 3)] : 0u;
         int dEp = 0, tw = 0;
         uint32_t r4[4] = {0u, 0u, 0u, 0u};
@@ -535,7 +545,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             // flat load that waits on both the vector and the LDS counters
             typedef __attribute__((address_space(3))) const RowV LdsRowV;
             typedef __attribute__((address_space(1))) const RowV GlobalRowV;
-            if (J.w_lds) raw = *(LdsRowV *)(Wl + (size_t)k * ld + col0);
+            if (w_lds) raw = *(LdsRowV *)(Wl + (size_t)k * ld + col0);
             else raw = *(GlobalRowV *)(reinterpret_cast<const WT *>(J.W) + (size_t)k * ld + col0);
         }
         if (NW > 1 && pend) {
@@ -565,12 +575,12 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 // lane reads its F slots and clears them.  LDS operations of
                 // one wave complete in order, so no barrier.
                 const int dw = delta * wscale;
-                const uint32_t *er = (J.w_lds ? reinterpret_cast<const uint32_t *>(smem) : J.ell) +
+                const uint32_t *er = (w_lds ? reinterpret_cast<const uint32_t *>(smem) : J.ell) +
                                      (size_t)k * J.ell_D;
                 const int base = wr * 64 * F;
                 for (int q0 = 0; q0 < J.ell_D; q0 += 64) {
                     const int j = min(q0 + lane, J.ell_D - 1);
-                    const uint32_t e = J.w_lds ? *(__attribute__((address_space(3))) const uint32_t *)(er + j)
+                    const uint32_t e = w_lds ? *(__attribute__((address_space(3))) const uint32_t *)(er + j)
                                                : er[j];
                     const int c = (int)(e & 0xFFFFu) - base;
                     if (q0 + lane < J.ell_D && (unsigned)c < (unsigned)(64 * F))
@@ -583,9 +593,18 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 for (int f = 0; f < F; ++f) h[f] += dv[f] * dw;
 #pragma unroll
                 for (int f = 0; f < F; ++f) dh[lane * F + f] = 0;
-            } else if (wscale == 1) {
+            } else if (mul24) {
+                // 8/16-bit couplings times a common factor below 2^23: each
+                // product is exact as a 24-bit multiply, which the compiler
+                // fuses with the add
+                const int dw = delta * wscale;
 #pragma unroll
-                for (int f = 0; f < F; ++f) h[f] += delta > 0 ? (int)raw[f] : -(int)raw[f];
+                for (int f = 0; f < F; ++f) h[f] = __mul24((int)raw[f], dw) + h[f];
+            } else if (wscale == 1) {
+                // h + (+-raw): xor with the sign, add the sign's two's-complement fix
+                const int sx = delta > 0 ? 0 : -1;
+#pragma unroll
+                for (int f = 0; f < F; ++f) h[f] = h[f] + ((int)raw[f] ^ sx) - sx;
             } else {
 #pragma unroll
                 for (int f = 0; f < F; ++f) h[f] += delta * ((int)raw[f] * wscale);
@@ -986,9 +1005,14 @@ template <typename WT, int F, bool TRACE, bool HELP>
 int launch_run_t(const JobDesc &J, const TraceDesc &T, int blocks, int threads, size_t lds,
                  void *stream) {
     const dim3 g(blocks), b(threads);
+    const bool wide = J.NW > 1 && !J.w_lds;
     if (J.lvl_of_rep) {
-        hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, false, kModePlain>), g, b, lds, S(stream),
-                           J, T);
+        if (wide)
+            hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, false, kModeWide>), g, b, lds,
+                               S(stream), J, T);
+        else
+            hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, false, kModePlain>), g, b, lds,
+                               S(stream), J, T);
         return (int)hipGetLastError();
     }
     const int mode = (J.single ? kModeSingle : 0) | (J.stepT ? kModePerStep : 0);
@@ -1023,8 +1047,12 @@ int launch_run_t(const JobDesc &J, const TraceDesc &T, int blocks, int threads, 
     }
     switch (mode) {
         case kModePlain:
-            hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, kModePlain>), g, b, lds,
-                               S(stream), J, T);
+            if (wide)
+                hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, kModeWide>), g, b, lds,
+                                   S(stream), J, T);
+            else
+                hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, kModePlain>), g, b, lds,
+                                   S(stream), J, T);
             break;
         case kModeSingle:
             hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, kModeSingle>), g, b, lds,
