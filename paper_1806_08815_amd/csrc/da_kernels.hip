@@ -488,6 +488,13 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
 #pragma unroll
             for (int q = 0; q < 4; ++q) r4[q] = rec[par * NW * 64 + min(q, NW - 1) * 64 + lane];
             tw = lane < NW ? twr : 0;
+            // keep these reads together: left to itself the compiler sinks
+            // the draw and record reads into the branches that use them, so
+            // the step would wait for LDS three times in a row
+            asm volatile("" ::"v"(r4[0]), "v"(r4[1]), "v"(r4[2]), "v"(r4[3]), "v"(tw), "v"(vs),
+                         "v"(dEp));
+        } else if (HELP) {
+            asm volatile("" ::"v"(vs));
         }
         int m, k = 0, xk = 0, dk = 0, bit = 0;
         if (NW == 1) {

@@ -44,6 +44,10 @@ def _q(kind, N, seed):
         return instances.random_qubo(N, seed, lo=-300, hi=300)
     if kind == "random_big":
         return instances.random_qubo(N, seed, lo=-40000, hi=40000)
+    if kind == "sk_huge":
+        # common factor 2^24 >= 2^23: 8/16-bit storage takes the full-width
+        # multiply in the field update
+        return instances.ising_to_qubo(instances.sk_bimodal(N, seed))[0] * 2**22
     raise ValueError(kind)
 
 
@@ -68,12 +72,14 @@ def test_energy(api, kind, N, dtype):
     ("random", 70, 0, 8, 2), ("random", 257, 2, 8, 1), ("gauss", 300, 0, 4, 1),
     ("sk", 513, 0, 8, 1), ("sk", 1000, 2, 8, 2), ("gauss", 1024, 4, 8, 1),
     ("random_big", 600, 4, 4, 1), ("sk", 1536, 1, 8, 1), ("sk", 1024, 2, 4, 1),
-    ("gauss", 2048, 0, 4, 1),
+    ("gauss", 2048, 0, 4, 1), ("sk_huge", 40, 0, 8, 1), ("sk_huge", 40, 2, 4, 1),
 ])
 def test_trace_parity(api, kind, N, dtype, F, rpw, rng):
     Q = _q(kind, N, 5)
     if kind == "gauss":
         T_hi, T_lo, inc = 3.0 * 2**16, 0.05 * 2**16, 2**16
+    elif kind == "sk_huge":
+        T_hi, T_lo, inc = 3.0 * N ** 0.5 * 2**22, 0.1 * 2**22, 2**22
     elif kind.startswith("random"):
         T_hi, T_lo, inc = 4000.0, 10.0, 50
     else:
