@@ -118,7 +118,7 @@ int validate_schedule(const da_schedule *s, std::string &err) {
 // RPW replicas per workgroup.  W goes to LDS when small (it then serves every
 // row fetch at LDS latency).
 LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch,
-                         bool anneal_mode) {
+                         bool anneal_mode, bool direct) {
     LaunchShape sh;
     const int stage = anneal_mode ? 1 : 0;
     int cus = 256;
@@ -161,9 +161,18 @@ LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch,
                    : 0;
     sh.threads = 64 * per * sh.RPW;
     sh.blocks = (R + sh.RPW - 1) / sh.RPW;
-    sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, sh.w_lds ? (int)w_bytes : 0, stage, sh.NH, sparse);
-    if (sh.lds > (size_t)device_lds_limit() && sh.w_lds) {
+    // direct tables (narrow bands) are staged too when the schedule has them;
+    // W gives way to them, and they give way when even that does not fit
+    sh.direct = anneal_mode && direct ? 1 : 0;
+    const size_t limit = (size_t)device_lds_limit();
+    sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, sh.w_lds ? (int)w_bytes : 0, stage, sh.NH, sparse,
+                           sh.direct);
+    if (sh.lds > limit && sh.w_lds) {
         sh.w_lds = 0;
+        sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0, stage, sh.NH, sparse, sh.direct);
+    }
+    if (sh.lds > limit && sh.direct) {
+        sh.direct = 0;
         sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0, stage, sh.NH, sparse);
     }
     return sh;
@@ -206,6 +215,7 @@ JobDesc make_job(const da_ctx *ctx, const LevelTables &lt, int32_t R, uint32_t r
     J.hdr = lt.d_hdr;
     J.brk = lt.d_brk;
     J.thr = lt.d_thr;
+    J.q8 = sh.direct ? lt.d_q8 : nullptr;
     return J;
 }
 
@@ -546,6 +556,7 @@ bool tune_enabled() {
 
 LaunchShape tuned_shape(da_ctx *ctx, const LevelTables &lt, int32_t R, int64_t steps,
                         const da_schedule &sched, hipStream_t s) {
+    const bool direct = lt.d_q8 != nullptr && sched.n_levels > 0;
     int dev = 0;
     (void)hipGetDevice(&dev);
     int rb = 1;
@@ -554,13 +565,13 @@ LaunchShape tuned_shape(da_ctx *ctx, const LevelTables &lt, int32_t R, int64_t s
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         auto it = g_tune.find(key);
-        if (it != g_tune.end()) return choose_shape(ctx, R, &it->second, true);
+        if (it != g_tune.end()) return choose_shape(ctx, R, &it->second, true, direct);
     }
     const int64_t window = std::min<int64_t>(steps, 384);
-    if (window < 64) return choose_shape(ctx, R, nullptr, true);
+    if (window < 64) return choose_shape(ctx, R, nullptr, true, direct);
     StateBuf scratch;
     std::string err;
-    if (!scratch.ensure(R, ctx->ld, err)) return choose_shape(ctx, R, nullptr, true);
+    if (!scratch.ensure(R, ctx->ld, err)) return choose_shape(ctx, R, nullptr, true, direct);
     hipEvent_t a = nullptr, b = nullptr;
     (void)hipEventCreate(&a);
     (void)hipEventCreate(&b);
@@ -570,7 +581,7 @@ LaunchShape tuned_shape(da_ctx *ctx, const LevelTables &lt, int32_t R, int64_t s
         for (int rpw : {1, 2, 4}) {
             for (int rng : {1, -1}) {
                 const da_launch cand{F, rpw, 0, rng};
-                const LaunchShape sh = choose_shape(ctx, R, &cand, true);
+                const LaunchShape sh = choose_shape(ctx, R, &cand, true, direct);
                 if (sh.RPW != rpw || sh.F != F || sh.threads > 1024 ||
                     sh.lds > (size_t)device_lds_limit())
                     continue;
@@ -604,12 +615,12 @@ LaunchShape tuned_shape(da_ctx *ctx, const LevelTables &lt, int32_t R, int64_t s
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     scratch.release();
-    if (best.flips_per_lane == 0) return choose_shape(ctx, R, nullptr, true);
+    if (best.flips_per_lane == 0) return choose_shape(ctx, R, nullptr, true, direct);
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         g_tune[key] = best;
     }
-    return choose_shape(ctx, R, &best, true);
+    return choose_shape(ctx, R, &best, true, direct);
 }
 
 int next_events(da_ctx *ctx, hipEvent_t &e0, hipEvent_t &e1) {
@@ -777,7 +788,7 @@ int enqueue_anneal(da_ctx *ctx, const da_schedule *schedule, int64_t replica_bas
     const LaunchShape sh =
         (launch == nullptr && trace_dev == nullptr && tune_enabled() && !jt.steps)
             ? tuned_shape(ctx, lt0, replicas, steps, *schedule, s)
-            : choose_shape(ctx, replicas, launch, true);
+            : choose_shape(ctx, replicas, launch, true, lt0.d_q8 != nullptr && !jt.steps);
     J = make_job(ctx, lt0, replicas, (uint32_t)replica_base, seed, steps, *schedule, sh);
     attach_step_tables(J, jt);
     J.s0 = step_begin;

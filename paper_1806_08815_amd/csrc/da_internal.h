@@ -26,12 +26,22 @@ namespace dapt {
 // bucket D holds (lo, hi) = (ucut(last d of the bucket), ucut(first d)) packed
 // as lo | hi << 16, so u < lo accepts, u >= hi rejects, and only lo <= u < hi
 // needs the table entry thr[u].  With sh = 0 the bracket is exact (lo == hi).
+//
+// Narrow bands (tmax - tmin <= kDirectSpan) also get a direct table of the
+// decision by draw: q[u] = thr[u] - tmin in [0, tmax - tmin], one byte per
+// draw, so an in-band flip with ub = d - tmin - 1 is accepted iff ub < q[u].
+// The table depends on the draw only, so it can be read before the flip's
+// cost is known.
 struct LevelHdr {
     int32_t tmin;
     int32_t tmax;
     int32_t sh;
     int32_t off;   // first bucket of this level in brk
+    int32_t q8;    // index of this level's direct table, or -1
+    int32_t pad[3];
 };
+constexpr int kDirectSpan = 255;
+constexpr int kMaxDirectLevels = 512;   // schedules with more levels use brackets only
 
 constexpr int kMaxBuckets = 4096;   // buckets per level
 constexpr int kMaxLevels = 4096;
@@ -50,7 +60,7 @@ struct StepT {
 
 // Compile-time feature sets of the step kernel (see run_block).
 constexpr int kModePlain = 0, kModeSingle = 1, kModePerStep = 2, kModeDynamic = 4,
-              kModeSparse = 8, kModeWide = 16;
+              kModeSparse = 8, kModeWide = 16, kModeDirect = 32;
 
 struct JobDesc {
     const void *W;
@@ -81,6 +91,7 @@ struct JobDesc {
     const int32_t *thr;
     const StepT *stepT;          // per-step schedule, else null
     const double *G;             // -ln U_u, with stepT
+    const uint8_t *q8;           // direct tables staged in LDS (anneal mode), or null
     int32_t single;              // 1: only variable s mod N proposes at step s
     int32_t ell_D;               // sparse row lists: entries per row (0: dense)
     const uint32_t *ell;         // [N][ell_D] column | value << 16, or null
@@ -166,8 +177,9 @@ __host__ __device__ inline SlotLayout slot_layout(int NW, int NH, int dhF = 0) {
 }
 
 // Workgroup LDS bytes the run kernel needs for a launch shape (stage_brk: the
-// level's bracket table is staged in LDS, anneal mode).
+// level's bracket table is staged in LDS, anneal mode; direct: so is a direct
+// table of 65536 bytes).
 size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk, int NH,
-                     bool sparse = false);
+                     bool sparse = false, bool direct = false);
 
 }  // namespace dapt

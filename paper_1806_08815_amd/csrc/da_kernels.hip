@@ -166,10 +166,10 @@ __device__ __forceinline__ int row16_incl_scan(int v) {
 }  // namespace
 
 size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk, int NH,
-                     bool sparse) {
+                     bool sparse, bool direct) {
     const SlotLayout SL = slot_layout(NW, NH, sparse ? F : 0);
     size_t w = (size_t)((w_lds_bytes + 15) & ~15);
-    size_t b = stage_brk ? (size_t)kMaxBuckets * 4 : 0;
+    size_t b = stage_brk ? (size_t)kMaxBuckets * 4 + (direct ? 65536 : 0) : 0;
     return w + b + (size_t)SL.bytes * RPW;
 }
 
@@ -201,6 +201,7 @@ size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk, int
 // the batched kernel when a batch mixes them).  kModeWide states that every
 // replica spans several compute waves and W is read from global memory, so
 // the single-wave and LDS-resident paths drop out of the step loop.
+// kModeDirect carries the direct-table decisions of narrow-band levels.
 template <typename WT, int F, bool TRACE, bool HELP, bool STAGE, int MODE>
 __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *smem,
                                           const TraceDesc &T) {
@@ -247,14 +248,19 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         s1 = s0 + J.K;
     }
 
-    // --- LDS carve-up: [W][brackets][per replica slot] -----------------------
+    // --- LDS carve-up: [W][brackets][direct table][per replica slot] ----------
     // LDS may hold dense W, or with sparse rows the row lists instead
     const int w_src = sparse ? J.N * J.ell_D * 4 : J.N * ld * (int)sizeof(WT);
     const int w_bytes = w_lds ? ((w_src + 15) & ~15) : 0;
     const WT *Wl = reinterpret_cast<const WT *>(smem);
     uint32_t *brk_l = reinterpret_cast<uint32_t *>(smem + w_bytes);
+    // direct tables (narrow bands, anneal mode): the level's 65536 decisions
+    constexpr bool dq = (MODE & kModeDirect) != 0;
+    const bool has_q = dq && stage && !perstep && J.q8 != nullptr;
+    const uint8_t *q_l = smem + w_bytes + kMaxBuckets * 4;
     const SlotLayout SL = slot_layout(NW, NH, sparse ? F : 0);
-    uint8_t *sel = smem + w_bytes + (stage ? kMaxBuckets * 4 : 0) + (size_t)SL.bytes * slot;
+    uint8_t *sel = smem + w_bytes + (stage ? kMaxBuckets * 4 + (has_q ? 65536 : 0) : 0) +
+                   (size_t)SL.bytes * slot;
     int *tot = reinterpret_cast<int *>(sel + SL.tot);              // [2][NW]
     uint32_t *rec = reinterpret_cast<uint32_t *>(sel + SL.rec);    // [2][NW*64]
     int *dEs = reinterpret_cast<int *>(sel + SL.dEs);              // [2]
@@ -315,13 +321,42 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         s_next = next_level_step(lvl, J.L, J.S);
     }
     LevelHdr hd = J.hdr[lvl];
+    bool direct = false;   // this level decides in-band flips by its direct table
     auto stage_brackets = [&]() {
         __syncthreads();
-        const int nb = hd.tmax > hd.tmin ? ((hd.tmax - hd.tmin - 1) >> hd.sh) + 1 : 0;
-        for (int q = threadIdx.x; q < nb; q += blockDim.x) brk_l[q] = J.brk[hd.off + q];
+        direct = has_q && hd.q8 >= 0;
+        if (direct) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(J.q8 + (size_t)hd.q8 * 65536);
+            uint4 *dst = reinterpret_cast<uint4 *>(smem + w_bytes + kMaxBuckets * 4);
+            const int bd = blockDim.x;
+            for (int q0 = threadIdx.x; q0 < 4096; q0 += 4 * bd) {
+                uint4 v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (q0 + i * bd < 4096) v[i] = src[q0 + i * bd];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (q0 + i * bd < 4096) dst[q0 + i * bd] = v[i];
+            }
+        } else {
+            const int nb = hd.tmax > hd.tmin ? ((hd.tmax - hd.tmin - 1) >> hd.sh) + 1 : 0;
+            for (int q = threadIdx.x; q < nb; q += blockDim.x) brk_l[q] = J.brk[hd.off + q];
+        }
         __syncthreads();
     };
     if (stage) stage_brackets();
+
+    // 16-bit draw of this lane's flip f from its Philox blocks
+    auto draw16 = [&](const uint4 (&r)[NB], int f) -> uint32_t {
+        const int slice = (F >= 8) ? (f & 7) : ((HELP ? 0 : (i0 & 7)) + f);
+        const uint32_t wv = word_of(r[f >> 3], slice >> 1);
+        return (slice & 1) ? (wv >> 16) : (wv & 0xFFFFu);
+    };
+    // direct-table decisions of this lane's flips for the draws in r
+    auto lookup_q = [&](const uint4 (&r)[NB], uint32_t (&q)[F]) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) q[f] = q_l[draw16(r, f)];
+    };
 
     // generator waves: the draws of step st into ring slot st & 1
     auto produce = [&](int64_t st) {
@@ -349,10 +384,18 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     };
 
     uint4 rb[NB];
+    // with random-number waves the direct-table decisions of a step are read
+    // one step ahead, as soon as its draws arrive
+    uint32_t qv[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) qv[f] = 0u;
     if (HELP) {
         if (helper) produce(s0);
         __syncthreads();
-        if (!helper) consume(s0, rb);
+        if (!helper) {
+            consume(s0, rb);
+            if (direct) lookup_q(rb, qv);
+        }
     }
 
     // single trial: the variable proposing at the current step (s mod N)
@@ -371,7 +414,10 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             s_next = next_level_step(lvl, J.L, J.S);
             to_next = s_next - s;
             hd = J.hdr[lvl];
-            if (stage) stage_brackets();
+            if (stage) {
+                stage_brackets();
+                if (HELP && !helper && direct) lookup_q(rb, qv);
+            }
         }
         const int par = (int)(s & 1);
         // per-step schedule: this step's temperature and band (loaded one
@@ -410,7 +456,21 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             // 2. in-band flips: 16-bit draw and bracket.  Every bracket read is
             // issued (out-of-band flips read entry 0) and waited on once; the
             // threshold table is read only inside a non-exact bracket (rare).
-            if (inb) {
+            if (inb && direct) {
+                // narrow band: ub = d - tmin - 1 is accepted iff ub < q[u]
+                if (!HELP) {
+#pragma unroll
+                    for (int q = 0; q < NB; ++q)
+                        rb[q] = philox((uint32_t)(i0 >> 3) + q, (uint32_t)s, rid, kTagMetropolis,
+                                       k0, k1);
+                    lookup_q(rb, qv);
+                }
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    const uint32_t ub = (uint32_t)(d[f] - hd.tmin - 1);
+                    acc |= (((inb >> f) & 1u) & (uint32_t)(ub < qv[f])) << f;
+                }
+            } else if (inb) {
                 if (!HELP) {
 #pragma unroll
                     for (int q = 0; q < NB; ++q)
@@ -555,6 +615,9 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             if (w_lds) raw = *(LdsRowV *)(Wl + (size_t)k * ld + col0);
             else raw = *(GlobalRowV *)(reinterpret_cast<const WT *>(J.W) + (size_t)k * ld + col0);
         }
+        // the next step's direct-table decisions (its draws arrived with this
+        // step's exchange); a level change re-reads them after staging
+        if (HELP && direct && left != 1) lookup_q(rbn, qv);
         if (NW > 1 && pend) {
             // the previous step's energy change (written by its owner lane)
             E += (int64_t)__builtin_amdgcn_readfirstlane(dEp);
@@ -1054,7 +1117,13 @@ int launch_run_t(const JobDesc &J, const TraceDesc &T, int blocks, int threads, 
     }
     switch (mode) {
         case kModePlain:
-            if (wide)
+            if (J.q8 && wide)
+                hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, kModeWide | kModeDirect>), g,
+                                   b, lds, S(stream), J, T);
+            else if (J.q8)
+                hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, kModeDirect>), g, b, lds,
+                                   S(stream), J, T);
+            else if (wide)
                 hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, kModeWide>), g, b, lds,
                                    S(stream), J, T);
             else

@@ -22,6 +22,7 @@ struct LevelTables {
     int32_t *d_thr = nullptr;      // [L][65536]
     LevelHdr *d_hdr = nullptr;     // [L]
     uint32_t *d_brk = nullptr;     // brackets of all levels
+    uint8_t *d_q8 = nullptr;       // direct tables [levels with q8 >= 0][65536], or null
     size_t bytes = 0;
     std::vector<LevelHdr> hdr;     // host copy (tests, footprints)
     ~LevelTables();
@@ -53,6 +54,7 @@ struct HostTables {
     std::vector<int32_t> thr;      // [L][65536]
     std::vector<LevelHdr> hdr;     // [L]
     std::vector<uint32_t> brk;
+    std::vector<uint8_t> q8;       // direct tables of the narrow-band levels
 };
 void build_host_tables(const std::vector<double> &temps, HostTables &ht);
 // Tables for a temperature list (cached per device); nullptr on failure with
@@ -87,6 +89,7 @@ struct LaunchShape {
     int NH = 0;         // random-number waves per replica (0: lazy draws)
     int RPW = 1;
     int w_lds = 0;
+    int direct = 0;     // the level's direct table is staged in LDS (anneal mode)
     int threads = 64;
     int blocks = 1;
     size_t lds = 0;
@@ -194,8 +197,9 @@ void set_thread_error(const std::string &msg);
 int fail(da_ctx *ctx, int code, const std::string &msg);
 int check_hip(da_ctx *ctx, hipError_t e, const char *what);
 int validate_schedule(const da_schedule *s, std::string &err);
+// direct: the schedule's tables include direct tables (staged when they fit)
 LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch,
-                         bool anneal_mode);
+                         bool anneal_mode, bool direct = false);
 // Fastest measured shape for this instance size, coupling type and replica
 // count (timed once on scratch state, then cached).
 LaunchShape tuned_shape(da_ctx *ctx, const LevelTables &lt, int32_t R, int64_t steps,

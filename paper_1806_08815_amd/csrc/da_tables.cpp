@@ -62,6 +62,8 @@ void build_brackets(const int32_t *thr, LevelHdr &hd, std::vector<uint32_t> &brk
     hd.tmin = thr[65535];
     hd.tmax = thr[0];
     hd.sh = 0;
+    hd.q8 = -1;
+    hd.pad[0] = hd.pad[1] = hd.pad[2] = 0;
     hd.off = (int32_t)brk.size();
     if (hd.tmax <= hd.tmin) return;   // no draw ever changes a decision
     const int64_t range = (int64_t)hd.tmax - hd.tmin;
@@ -94,13 +96,16 @@ std::vector<double> schedule_temps(const da_schedule &s) {
 }
 
 int64_t level_table_bytes(int32_t L, int64_t buckets) {
-    return (int64_t)L * 65536 * 4 + (int64_t)L * (int64_t)sizeof(LevelHdr) + buckets * 4;
+    // direct tables: at most one per level, only for short schedules
+    const int64_t q8 = L <= kMaxDirectLevels ? (int64_t)L * 65536 : 0;
+    return (int64_t)L * 65536 * 4 + (int64_t)L * (int64_t)sizeof(LevelHdr) + buckets * 4 + q8;
 }
 
 LevelTables::~LevelTables() {
     if (d_thr) (void)hipFree(d_thr);
     if (d_hdr) (void)hipFree(d_hdr);
     if (d_brk) (void)hipFree(d_brk);
+    if (d_q8) (void)hipFree(d_q8);
 }
 
 namespace {
@@ -121,9 +126,18 @@ void build_host_tables(const std::vector<double> &temps, HostTables &ht) {
     ht.thr.resize(L * 65536);
     ht.hdr.resize(L);
     ht.brk.clear();
+    ht.q8.clear();
+    int32_t nq = 0;
     for (size_t l = 0; l < L; ++l) {
+        const int32_t *thr = ht.thr.data() + l * 65536;
         build_threshold_table(temps[l], ht.thr.data() + l * 65536);
-        build_brackets(ht.thr.data() + l * 65536, ht.hdr[l], ht.brk);
+        build_brackets(thr, ht.hdr[l], ht.brk);
+        LevelHdr &hd = ht.hdr[l];
+        if (L <= (size_t)kMaxDirectLevels && hd.tmax > hd.tmin &&
+            hd.tmax - hd.tmin <= kDirectSpan) {
+            hd.q8 = nq++;
+            for (int u = 0; u < 65536; ++u) ht.q8.push_back((uint8_t)(thr[u] - hd.tmin));
+        }
     }
     if (ht.brk.empty()) ht.brk.push_back(0);
 }
@@ -153,18 +167,21 @@ std::shared_ptr<LevelTables> get_level_tables(const std::vector<double> &temps, 
     lt->hdr = pre->hdr;
     const size_t thr_b = pre->thr.size() * 4, hdr_b = pre->hdr.size() * sizeof(LevelHdr),
                  brk_b = pre->brk.size() * 4;
+    const size_t q8_b = pre->q8.size();
     if (hipMalloc(&lt->d_thr, thr_b) != hipSuccess || hipMalloc(&lt->d_hdr, hdr_b) != hipSuccess ||
-        hipMalloc(&lt->d_brk, brk_b) != hipSuccess) {
+        hipMalloc(&lt->d_brk, brk_b) != hipSuccess ||
+        (q8_b && hipMalloc(&lt->d_q8, q8_b) != hipSuccess)) {
         err = "out of device memory for level tables";
         return nullptr;
     }
     if (hipMemcpy(lt->d_thr, pre->thr.data(), thr_b, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(lt->d_hdr, pre->hdr.data(), hdr_b, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(lt->d_brk, pre->brk.data(), brk_b, hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(lt->d_brk, pre->brk.data(), brk_b, hipMemcpyHostToDevice) != hipSuccess ||
+        (q8_b && hipMemcpy(lt->d_q8, pre->q8.data(), q8_b, hipMemcpyHostToDevice) != hipSuccess)) {
         err = "upload of level tables failed";
         return nullptr;
     }
-    lt->bytes = thr_b + hdr_b + brk_b;
+    lt->bytes = thr_b + hdr_b + brk_b + q8_b;
     g_cache[key] = lt;
     return lt;
 }
