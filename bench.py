@@ -320,6 +320,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="torus2d-bimodal-1024")
     ap.add_argument("--dtype", type=int, default=None, help="force coupling storage bytes")
+    ap.add_argument("--launch", default=None,
+                    help="fixed step-kernel shape F:RPW:RNG (flips per lane, replicas per "
+                         "workgroup, random-number waves: 1 on, -1 off) instead of the tuned one")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-extras", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=24,
@@ -351,8 +354,13 @@ def main() -> int:
     stream = torch.cuda.current_stream()
     out = api.device_outputs(R, N)
 
+    fixed = None
+    if args.launch:
+        F_, rpw_, rng_ = (int(v) for v in args.launch.split(":"))
+        fixed = api.launch(F_, rpw_, 0, rng_)
+
     def anneal():
-        api.da_anneal_async(ctx, sch, 0, R, S, w.seed, None, out, stream)
+        api.da_anneal_async(ctx, sch, 0, R, S, w.seed, fixed, out, stream)
 
     print(f"[bench] {describe(w)}; storage int{8 * info['dtype']} x{info['wscale']}",
           file=sys.stderr, flush=True)

@@ -329,14 +329,16 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             const uint4 *src = reinterpret_cast<const uint4 *>(J.q8 + (size_t)hd.q8 * 65536);
             uint4 *dst = reinterpret_cast<uint4 *>(smem + w_bytes + kMaxBuckets * 4);
             const int bd = blockDim.x;
+            // four loads in flight per thread; indices past the end are
+            // clamped, so the last piece is just copied more than once
             for (int q0 = threadIdx.x; q0 < 4096; q0 += 4 * bd) {
-                uint4 v[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (q0 + i * bd < 4096) v[i] = src[q0 + i * bd];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (q0 + i * bd < 4096) dst[q0 + i * bd] = v[i];
+                const int q1 = min(q0 + bd, 4095), q2 = min(q0 + 2 * bd, 4095),
+                          q3 = min(q0 + 3 * bd, 4095);
+                const uint4 a = src[q0], b = src[q1], c = src[q2], e = src[q3];
+                dst[q0] = a;
+                dst[q1] = b;
+                dst[q2] = c;
+                dst[q3] = e;
             }
         } else {
             const int nb = hd.tmax > hd.tmin ? ((hd.tmax - hd.tmin - 1) >> hd.sh) + 1 : 0;
@@ -347,13 +349,14 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     if (stage) stage_brackets();
 
     // 16-bit draw of this lane's flip f from its Philox blocks
-    auto draw16 = [&](const uint4 (&r)[NB], int f) -> uint32_t {
+    // (forced inline: an out-of-line copy would keep the arrays in scratch)
+    auto draw16 = [&](const uint4 (&r)[NB], int f) __attribute__((always_inline)) -> uint32_t {
         const int slice = (F >= 8) ? (f & 7) : ((HELP ? 0 : (i0 & 7)) + f);
         const uint32_t wv = word_of(r[f >> 3], slice >> 1);
         return (slice & 1) ? (wv >> 16) : (wv & 0xFFFFu);
     };
     // direct-table decisions of this lane's flips for the draws in r
-    auto lookup_q = [&](const uint4 (&r)[NB], uint32_t (&q)[F]) {
+    auto lookup_q = [&](const uint4 (&r)[NB], uint32_t (&q)[F]) __attribute__((always_inline)) {
 #pragma unroll
         for (int f = 0; f < F; ++f) q[f] = q_l[draw16(r, f)];
     };
