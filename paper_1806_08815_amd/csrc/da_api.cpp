@@ -163,7 +163,8 @@ LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch,
     sh.blocks = (R + sh.RPW - 1) / sh.RPW;
     // direct tables (narrow bands) are staged too when the schedule has them;
     // W gives way to them, and they give way when even that does not fit
-    sh.direct = anneal_mode && direct ? 1 : 0;
+    // (sparse row lists take a kernel variant without them)
+    sh.direct = anneal_mode && direct && !sparse ? 1 : 0;
     const size_t limit = (size_t)device_lds_limit();
     sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, sh.w_lds ? (int)w_bytes : 0, stage, sh.NH, sparse,
                            sh.direct);
@@ -554,9 +555,15 @@ bool tune_enabled() {
 }
 }  // namespace
 
+// Direct tables pay for their staging (64 KiB per level and workgroup) only
+// when levels last a few hundred steps.
+static bool want_direct(const LevelTables &lt, const da_schedule &sched, int64_t steps) {
+    return lt.d_q8 != nullptr && sched.n_levels > 0 && steps >= 256 * (int64_t)sched.n_levels;
+}
+
 LaunchShape tuned_shape(da_ctx *ctx, const LevelTables &lt, int32_t R, int64_t steps,
                         const da_schedule &sched, hipStream_t s) {
-    const bool direct = lt.d_q8 != nullptr && sched.n_levels > 0;
+    const bool direct = want_direct(lt, sched, steps);
     int dev = 0;
     (void)hipGetDevice(&dev);
     int rb = 1;
@@ -788,7 +795,7 @@ int enqueue_anneal(da_ctx *ctx, const da_schedule *schedule, int64_t replica_bas
     const LaunchShape sh =
         (launch == nullptr && trace_dev == nullptr && tune_enabled() && !jt.steps)
             ? tuned_shape(ctx, lt0, replicas, steps, *schedule, s)
-            : choose_shape(ctx, replicas, launch, true, lt0.d_q8 != nullptr && !jt.steps);
+            : choose_shape(ctx, replicas, launch, true, !jt.steps && want_direct(lt0, *schedule, steps));
     J = make_job(ctx, lt0, replicas, (uint32_t)replica_base, seed, steps, *schedule, sh);
     attach_step_tables(J, jt);
     J.s0 = step_begin;

@@ -34,6 +34,9 @@ def _same(a, b):
     (200, 7, 3000, 16, [1, 1500, 2999], "zeros"),       # mid-level cuts, one-step pieces
     (1024, 5, 2048, 8, [256, 512, 1024], "random"),    # cuts on level boundaries
     (64, 33, 1000, 128, [333, 777], "zeros"),
+    # >= 256 steps per level: narrow-band levels decide by direct tables; cuts
+    # mid-level and one step before a level change
+    (300, 5, 2400, 4, [1, 700, 1199, 2399], "zeros"),
 ])
 def test_split_equals_one_shot(api, N, R, S, L, cuts, init):
     Q = instances.ising_to_qubo(instances.sk_bimodal(N, 21))[0]

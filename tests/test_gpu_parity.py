@@ -93,6 +93,27 @@ def test_trace_parity(api, kind, N, dtype, F, rpw, rng):
     _same(gpu, ref, ("trace_k", "trace_E", "trace_eoff") + KEYS)
 
 
+@pytest.mark.parametrize("rng", [1, -1])
+@pytest.mark.parametrize("kind,N,dtype,F,rpw", [
+    ("sk", 64, 0, 4, 1), ("sk", 100, 4, 8, 3), ("sk", 300, 2, 4, 1), ("sk", 1024, 2, 4, 1),
+    ("sk", 1000, 1, 8, 2),
+])
+def test_direct_table_trace_parity(api, kind, N, dtype, F, rpw, rng):
+    """Levels of at least 256 steps: the narrow-band levels (tmax - tmin <= 255)
+    decide in-band flips by their direct tables, read a step ahead; the hottest
+    level's band is wider and takes the brackets, so runs cross both kinds of
+    level change."""
+    Q = _q(kind, N, 7)
+    T_hi, T_lo, inc = 3.0 * max(1.0, N ** 0.5), 0.1, 1
+    R, S, L = 4, 1600, 4
+    ctx = api.da_create(Q, dtype)
+    sch = api.schedule(T_hi, T_lo, "geometric", L, eoff_inc=inc)
+    gpu = api.da_anneal_ex(ctx, sch, 1, R, S, 23, api.launch(F, rpw, 0, rng), trace=True)
+    ref = oracle.anneal(Q, T_hi=T_hi, T_lo=T_lo, n_levels=L, eoff_inc=inc, replica_base=1,
+                        replicas=R, steps=S, seed=23, trace=True)
+    _same(gpu, ref, ("trace_k", "trace_E", "trace_eoff") + KEYS)
+
+
 @pytest.mark.parametrize("w_lds", [1, -1])
 def test_sk_bimodal_64_full(api, w_lds):
     """16 replicas x 10^4 steps of an N = 64 +-1 SK instance, escape offset on."""
