@@ -96,15 +96,18 @@ def test_trace_parity(api, kind, N, dtype, F, rpw, rng):
 @pytest.mark.parametrize("rng", [1, -1])
 @pytest.mark.parametrize("kind,N,dtype,F,rpw", [
     ("sk", 64, 0, 4, 1), ("sk", 100, 4, 8, 3), ("sk", 300, 2, 4, 1), ("sk", 1024, 2, 4, 1),
-    ("sk", 1000, 1, 8, 2),
+    ("sk", 1000, 1, 8, 2), ("gauss", 1024, 0, 8, 1), ("gauss", 513, 4, 4, 2),
 ])
 def test_direct_table_trace_parity(api, kind, N, dtype, F, rpw, rng):
     """Levels of at least 256 steps: the narrow-band levels (tmax - tmin <= 255)
-    decide in-band flips by their direct tables, read a step ahead; the hottest
-    level's band is wider and takes the brackets, so runs cross both kinds of
-    level change."""
+    decide in-band flips by their direct tables, read a step ahead; wider bands
+    (the hottest +-1 level, every Gaussian level) take the brackets, so runs
+    cross both kinds of level change."""
     Q = _q(kind, N, 7)
-    T_hi, T_lo, inc = 3.0 * max(1.0, N ** 0.5), 0.1, 1
+    if kind == "gauss":
+        T_hi, T_lo, inc = 3.0 * 2**16, 0.05 * 2**16, 2**16
+    else:
+        T_hi, T_lo, inc = 3.0 * max(1.0, N ** 0.5), 0.1, 1
     R, S, L = 4, 1600, 4
     ctx = api.da_create(Q, dtype)
     sch = api.schedule(T_hi, T_lo, "geometric", L, eoff_inc=inc)
