@@ -520,7 +520,7 @@ def main() -> int:
                                                      kind="linear_beta", n_levels=0)
         INT8_PEAK_TOPS = 5000.0
         fm = {}
-        for n, r in ((1024, 2048), (8192, 8192)):
+        for n, r in ((1024, 1024), (1024, 2048), (8192, 8192)):
             p = api.da_probe_fields_mfma(n, r, 10)
             fm[f"N{n}_R{r}"] = {**p, "frac_of_int8_peak": p["tera_ops"] / INT8_PEAK_TOPS}
         result["initial_fields_mfma"] = fm

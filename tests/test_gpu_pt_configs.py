@@ -149,3 +149,23 @@ def test_random_start_tiled_mfma_fields(api):
                             replica_base=r, replicas=1, steps=60, seed=13)
         for k in KEYS:
             assert np.array_equal(gpu[k][r], ref[k][0]), (r, k)
+
+def test_random_start_large_mfma_fields(api):
+    """A larger random start on the LDS-tiled MFMA field kernel (ragged in both
+    directions, many blocks per CU): exact energies of every random start state,
+    and the oracle's trajectories for sampled replicas."""
+    N, R = 1950, 4500
+    Q = instances.ising_to_qubo(instances.sk_bimodal(N, 37))[0]
+    ctx = api.da_create(Q)
+    assert ctx.info()["dtype"] == 1
+    sch = api.schedule(3.0 * N ** 0.5, 0.1, "geometric", 16, 1, "random")
+    g0 = api.da_anneal_ex(ctx, sch, 0, R, 0, 19)
+    X = g0["final_x"].astype(np.float64)
+    E = ((X @ Q.astype(np.float64)) * X).sum(axis=1)   # exact: integers below 2^53
+    assert np.array_equal(g0["final_E"], E.astype(np.int64))
+    gpu = api.da_anneal_ex(ctx, sch, 0, R, 40, 19)
+    for r in (0, 2303, R - 1):
+        ref = oracle.anneal(Q, T_hi=3.0 * N ** 0.5, T_lo=0.1, n_levels=16, eoff_inc=1, init=1,
+                            replica_base=r, replicas=1, steps=40, seed=19)
+        for k in KEYS:
+            assert np.array_equal(gpu[k][r], ref[k][0]), (r, k)
