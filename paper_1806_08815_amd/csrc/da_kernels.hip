@@ -567,7 +567,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                                         : philox(0u, (uint32_t)s, rid, kTagSelect, k0, k1).x;
                 const int j = (int)(((uint64_t)v * (uint32_t)m) >> 32);
                 const uint64_t bal = ballot(excl + c > j);
-                const int ts = __ffsll((unsigned long long)bal) - 1;
+                const int ts = (int)__builtin_ctzll(bal);
                 const int rloc = j - readlane(excl, ts);
                 const uint32_t msk = (uint32_t)readlane((int)acc, ts);
                 bit = select_bit<F>(msk, rloc);
@@ -585,8 +585,8 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 const uint32_t v = HELP ? (uint32_t)__builtin_amdgcn_readfirstlane((int)vs)
                                         : philox(0u, (uint32_t)s, rid, kTagSelect, k0, k1).x;
                 const int j = (int)(((uint64_t)v * (uint32_t)m) >> 32);
-                const uint64_t wbal = ballot(lane < NW && scan > j);
-                const int ws = __ffsll((unsigned long long)wbal) - 1;
+                const uint64_t wbal = ballot(scan > j) & ((1ull << NW) - 1ull);
+                const int ws = (int)__builtin_ctzll(wbal);
                 const int jw = j - (readlane(scan, ws) - readlane(tw, ws));
                 uint32_t r2;
                 if (NW <= 4) {
@@ -598,7 +598,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 }
                 // first lane of wave ws whose inclusive prefix passes jw
                 const uint64_t bal = ballot((int)(r2 >> 16) > jw);
-                const int ts = __ffsll((unsigned long long)bal) - 1;
+                const int ts = (int)__builtin_ctzll(bal);
                 const uint32_t rs = (uint32_t)readlane((int)r2, ts);
                 const int rloc = jw - ((int)(rs >> 16) - __popc(rs & 0xFFu));
                 bit = select_bit<F>(rs & 0xFFu, rloc);
