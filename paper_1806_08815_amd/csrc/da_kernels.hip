@@ -228,6 +228,10 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     const int g = wr * 64 + lane;
     const int i0 = g * F;
     const int rr = blk * J.RPW + slot;
+    // waves beyond the replica slots (the batched kernel always runs 16) hold
+    // no replica and only keep the barrier count: their slot has fewer than NW
+    // waves, so its exchange data would never be complete
+    const bool idle = !helper && slot >= J.RPW;
     const bool active = (slot < J.RPW) && (rr < J.R);
     const bool lane_has = !helper && active && (i0 < J.ld);
     const int col0 = lane_has ? i0 : 0;     // row column this lane reads (ghost lanes: 0)
@@ -438,7 +442,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
 
         if (helper) {
             if (left != 1) produce(s + 1);
-        } else {
+        } else if (!idle) {
             // 1. cost of every flip and the draw-free decisions (branch-free)
             uint32_t inb = 0;
 #pragma unroll
@@ -535,7 +539,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             }
         }
         if (sync) __syncthreads();
-        if (helper) continue;
+        if (helper || idle) continue;
 
         // 3b. the chosen flip.  Everything this step needs from LDS is read
         // in one straight-line group (clamped indices, no branches), so the
@@ -579,7 +583,15 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 dk = readlane(dsel, ts);
             }
         } else {
-            const int scan = row16_incl_scan(tw);
+            // wave totals sit in lanes 0..NW-1: a scan over 4 lanes suffices
+            // for up to 4 waves
+            int scan = tw;
+            scan += __builtin_amdgcn_update_dpp(0, scan, 0x111, 0xf, 0xf, false);  // row_shr:1
+            scan += __builtin_amdgcn_update_dpp(0, scan, 0x112, 0xf, 0xf, false);  // row_shr:2
+            if (NW > 4) {
+                scan += __builtin_amdgcn_update_dpp(0, scan, 0x114, 0xf, 0xf, false);  // row_shr:4
+                scan += __builtin_amdgcn_update_dpp(0, scan, 0x118, 0xf, 0xf, false);  // row_shr:8
+            }
             m = readlane(scan, NW - 1);
             if (m > 0) {
                 const uint32_t v = HELP ? (uint32_t)__builtin_amdgcn_readfirstlane((int)vs)
