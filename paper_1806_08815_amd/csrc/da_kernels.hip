@@ -202,7 +202,9 @@ size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk, int
 // replica spans several compute waves and W is read from global memory, so
 // the single-wave and LDS-resident paths drop out of the step loop.
 // kModeDirect carries the direct-table decisions of narrow-band levels.
-template <typename WT, int F, bool TRACE, bool HELP, bool STAGE, int MODE>
+// BATCH: the persistent batched kernel, whose workgroups may hold more waves
+// than the job's replica slots.
+template <typename WT, int F, bool TRACE, bool HELP, bool STAGE, int MODE, bool BATCH = false>
 __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *smem,
                                           const TraceDesc &T) {
     const bool single = MODE == kModeDynamic ? J.single != 0 : (MODE & kModeSingle) != 0;
@@ -231,7 +233,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     // waves beyond the replica slots (the batched kernel always runs 16) hold
     // no replica and only keep the barrier count: their slot has fewer than NW
     // waves, so its exchange data would never be complete
-    const bool idle = !helper && slot >= J.RPW;
+    const bool idle = BATCH && !helper && slot >= J.RPW;
     const bool active = (slot < J.RPW) && (rr < J.R);
     const bool lane_has = !helper && active && (i0 < J.ld);
     const int col0 = lane_has ? i0 : 0;     // row column this lane reads (ghost lanes: 0)
@@ -443,16 +445,28 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         if (helper) {
             if (left != 1) produce(s + 1);
         } else if (!idle) {
-            // 1. cost of every flip and the draw-free decisions (branch-free)
-            uint32_t inb = 0;
+            // 1. cost of every flip and the draw-free decisions (branch-free).
+            // Without direct tables the band tmin < d <= tmax is tested as one
+            // unsigned compare of ub = d - (tmin + 1) against tmax - tmin, and
+            // ub also indexes the brackets (measured faster there; with direct
+            // tables the two-compare form is)
+            const int t1 = hd.tmin + 1;
+            const uint32_t span = (uint32_t)(hd.tmax - hd.tmin);
+            uint32_t inb = 0, ub[F];
 #pragma unroll
             for (int f = 0; f < F; ++f) {
                 const int hv = h[f];
                 const int dd = (((xb >> f) & 1u) ? -hv : hv) - eoff;
                 d[f] = dd;
                 const uint32_t v = (vmask >> f) & 1u;
-                acc |= (v & (uint32_t)(dd <= hd.tmin)) << f;
-                inb |= (v & (uint32_t)(dd > hd.tmin) & (uint32_t)(dd <= hd.tmax)) << f;
+                if constexpr (dq) {
+                    acc |= (v & (uint32_t)(dd <= hd.tmin)) << f;
+                    inb |= (v & (uint32_t)(dd > hd.tmin) & (uint32_t)(dd <= hd.tmax)) << f;
+                } else {
+                    ub[f] = (uint32_t)dd - (uint32_t)t1;
+                    acc |= (v & (uint32_t)(dd < t1)) << f;
+                    inb |= (v & (uint32_t)(ub[f] < span)) << f;
+                }
             }
             // single-trial mode: only variable s mod N proposes this step
             if (single) {
@@ -508,7 +522,9 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                     const int slice = (F >= 8) ? (f & 7) : ((HELP ? 0 : (i0 & 7)) + f);
                     const uint32_t wv = word_of(rb[f >> 3], slice >> 1);
                     u[f] = (slice & 1) ? (wv >> 16) : (wv & 0xFFFFu);
-                    const int bi = ((inb >> f) & 1u) ? ((d[f] - hd.tmin - 1) >> hd.sh) : 0;
+                    // out-of-band flips read a valid bucket they then ignore
+                    const int bi = dq ? (((inb >> f) & 1u) ? ((d[f] - hd.tmin - 1) >> hd.sh) : 0)
+                                      : (int)(min(ub[f], span - 1u) >> hd.sh);
                     e[f] = stage ? brk_l[bi] : J.brk[hd.off + bi];
                 }
                 uint32_t fine = 0;
@@ -784,9 +800,9 @@ __global__ __launch_bounds__(1024) void k_batch(const JobDesc *__restrict__ jobs
         const BatchItem bi = items[it];
         JobDesc J = jobs[bi.job];
         const int blk = bi.r0 / J.RPW;
-        if (J.dtype == 1) run_block<int8_t, F, false, false, true, MODE>(J, blk, smem, T);
-        else if (J.dtype == 2) run_block<int16_t, F, false, false, true, MODE>(J, blk, smem, T);
-        else run_block<int32_t, F, false, false, true, MODE>(J, blk, smem, T);
+        if (J.dtype == 1) run_block<int8_t, F, false, false, true, MODE, true>(J, blk, smem, T);
+        else if (J.dtype == 2) run_block<int16_t, F, false, false, true, MODE, true>(J, blk, smem, T);
+        else run_block<int32_t, F, false, false, true, MODE, true>(J, blk, smem, T);
         __syncthreads();
     }
 }
