@@ -76,10 +76,13 @@ def test_batch_matches_alone(api):
 
 
 def test_batch_large_n(api):
-    """Batches holding the largest sizes (one replica per workgroup) beside small jobs."""
+    """Batches holding the largest sizes (one replica per workgroup) beside small jobs;
+    N = 6000 and N = 1500 leave surplus waves in their workgroups (12 and 3 x 5 of 16),
+    the last block of N = 1500 also holds empty replica slots."""
     import torch
     specs = [("sk", 8192, 3, 300, "zeros", 0, 8), ("gauss", 4096, 5, 500, "random", 0, 16),
-             ("sk", 64, 40, 800, "zeros", 0, 16), ("gauss", 6000, 2, 200, "zeros", 4, 4)]
+             ("sk", 64, 40, 800, "zeros", 0, 16), ("gauss", 6000, 2, 200, "zeros", 4, 4),
+             ("sk", 1500, 7, 300, "zeros", 0, 8)]
     items, alone = [], []
     for a, (kind, N, R, S, init, hint, L) in enumerate(specs):
         Q, t = _job(kind, N, 70 + a)
