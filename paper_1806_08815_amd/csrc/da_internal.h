@@ -31,7 +31,8 @@ namespace dapt {
 // decision by draw: q[u] = thr[u] - tmin in [0, tmax - tmin], one byte per
 // draw, so an in-band flip with ub = d - tmin - 1 is accepted iff ub < q[u].
 // The table depends on the draw only, so it can be read before the flip's
-// cost is known.
+// cost is known.  Such levels also have |tmin| <= kDirectTmin (always true of
+// a narrow band, as thr >= -1; stated so that tmin + 1 + E_off + q fits int32).
 struct LevelHdr {
     int32_t tmin;
     int32_t tmax;
@@ -41,6 +42,7 @@ struct LevelHdr {
     int32_t pad[3];
 };
 constexpr int kDirectSpan = 255;
+constexpr int kDirectTmin = 256;
 constexpr int kMaxDirectLevels = 512;   // schedules with more levels use brackets only
 
 constexpr int kMaxBuckets = 4096;   // buckets per level
@@ -142,21 +144,20 @@ int launch_fill_i32(int32_t *dst, int32_t value, int64_t n, void *stream);
 int device_lds_limit();
 
 // LDS of one replica slot of a workgroup (byte offsets): the selection
-// exchange of multi-wave replicas (wave totals, lane records, the energy
-// hand-off) and, with random-number waves, the selection-draw ring and the
+// exchange of multi-wave replicas (lane records, the energy hand-off) and, with random-number waves, the selection-draw ring and the
 // double-buffered Philox blocks; with sparse row lists (dhF = flips per lane)
 // one field-delta buffer of 64 * dhF int32 per compute wave.
 struct SlotLayout {
-    int tot, rec, dEs, vring, draws, dh, bytes;
+    int rec, dEs, vring, draws, dh, bytes;
 };
 __host__ __device__ inline SlotLayout slot_layout(int NW, int NH, int dhF = 0) {
-    SlotLayout L{0, 0, 0, 0, 0, 0, 0};
+    SlotLayout L{0, 0, 0, 0, 0, 0};
     int off = 0;
     if (NW > 1 || NH > 0) {
-        L.tot = off;
-        off += 2 * NW * 4;
+        // lane records [2][max(NW, 4) * 64]: four waves' records can always be
+        // read at fixed offsets (the entries past NW are never selected)
         L.rec = off;
-        off += 2 * NW * 64 * 4;
+        off += 2 * (NW > 4 ? NW : 4) * 64 * 4;
         L.dEs = off;
         off += 8;
     }

@@ -143,6 +143,23 @@ __device__ __forceinline__ void load_row(const WT *p, int (&w)[F]) {
     for (int f = 0; f < F; ++f) w[f] = (int)v[f];
 }
 
+// h[f] += raw[f] * dw for 16-bit couplings and |dw| < 2^15: one 16 x 16 -> 32
+// bit multiply-add per field, which takes the coupling in place from its half
+// of the loaded dword (op_sel selects the high half).
+template <typename WT, int F>
+__device__ __forceinline__ void update_i16(const typename VecOf<WT, F>::type &raw, int dw,
+                                           int (&h)[F]) {
+    if constexpr (sizeof(WT) == 2) {
+        typedef typename VecOf<int, F / 2>::type PairV;
+        const PairV pr = __builtin_bit_cast(PairV, raw);
+#pragma unroll
+        for (int q = 0; q < F / 2; ++q) {
+            asm("v_mad_i32_i16 %0, %1, %2, %0" : "+v"(h[2 * q]) : "v"(pr[q]), "s"(dw));
+            asm("v_mad_i32_i16 %0, %1, %2, %0 op_sel:[1,0,0,0]" : "+v"(h[2 * q + 1]) : "v"(pr[q]), "s"(dw));
+        }
+    }
+}
+
 // Level in force at step s of an S-step, L-level schedule: floor(s L / S).
 __device__ __forceinline__ int level_of(int64_t s, int32_t L, int64_t S) {
     return S > 0 ? (int)((s * (int64_t)L) / S) : 0;
@@ -199,8 +216,9 @@ size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk, int
 // none of their code: kModeSingle (single-trial proposals), kModePerStep (a new
 // temperature every step), both, or kModeDynamic (read from the job; used by
 // the batched kernel when a batch mixes them).  kModeWide states that every
-// replica spans several compute waves and W is read from global memory, so
-// the single-wave and LDS-resident paths drop out of the step loop.
+// replica spans several compute waves, W is read from global memory and
+// 16-bit couplings have a common factor below 2^15, so the single-wave,
+// LDS-resident and 24-bit update paths drop out of the step loop.
 // kModeDirect carries the direct-table decisions of narrow-band levels.
 // BATCH: the persistent batched kernel, whose workgroups may hold more waves
 // than the job's replica slots.
@@ -236,12 +254,17 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     const bool idle = BATCH && !helper && slot >= J.RPW;
     const bool active = (slot < J.RPW) && (rr < J.R);
     const bool lane_has = !helper && active && (i0 < J.ld);
+    // every flip of this wave is a variable of an active replica
+    const bool full = active && !helper && (wr + 1) * 64 * F <= J.N;
     const int col0 = lane_has ? i0 : 0;     // row column this lane reads (ghost lanes: 0)
     const uint32_t rid = J.rid_base + (uint32_t)rr;
     const uint32_t k0 = (uint32_t)J.seed;
     const uint32_t k1 = (uint32_t)(J.seed >> 32);
     const int ld = J.ld;
     const int wscale = J.wscale;
+    // the wide variants run 16-bit couplings only with a factor below 2^15
+    const bool mul16 =
+        sizeof(WT) == 2 && (wide || (wscale < (1 << 15) && wscale > -(1 << 15)));
     const bool mul24 = sizeof(WT) < 4 && wscale < (1 << 23) && wscale > -(1 << 23);
     constexpr bool stage = STAGE;
     const bool sync = HELP || NW > 1;       // a workgroup barrier every step
@@ -267,8 +290,9 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     const SlotLayout SL = slot_layout(NW, NH, sparse ? F : 0);
     uint8_t *sel = smem + w_bytes + (stage ? kMaxBuckets * 4 + (has_q ? 65536 : 0) : 0) +
                    (size_t)SL.bytes * slot;
-    int *tot = reinterpret_cast<int *>(sel + SL.tot);              // [2][NW]
-    uint32_t *rec = reinterpret_cast<uint32_t *>(sel + SL.rec);    // [2][NW*64]
+    // lane records by step parity; a wave's total is its last lane's prefix
+    const int RS = max(NW, 4) * 64;
+    uint32_t *rec = reinterpret_cast<uint32_t *>(sel + SL.rec);    // [2][RS]
     int *dEs = reinterpret_cast<int *>(sel + SL.dEs);              // [2]
     uint32_t *vring = reinterpret_cast<uint32_t *>(sel + SL.vring);  // [4] selection draws
     uint4 *draws = reinterpret_cast<uint4 *>(sel + SL.draws);      // [2][NH*64] Philox blocks
@@ -328,9 +352,11 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     }
     LevelHdr hd = J.hdr[lvl];
     bool direct = false;   // this level decides in-band flips by its direct table
+    bool fast = false;     // ... and this wave does so with one compare per flip
     auto stage_brackets = [&]() {
         __syncthreads();
         direct = has_q && hd.q8 >= 0;
+        fast = dq && HELP && direct && full;
         if (direct) {
             const uint4 *src = reinterpret_cast<const uint4 *>(J.q8 + (size_t)hd.q8 * 65536);
             uint4 *dst = reinterpret_cast<uint4 *>(smem + w_bytes + kMaxBuckets * 4);
@@ -417,7 +443,23 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     // only: 64-bit equality is a scalar compare, ordering is not
     int64_t to_next = s_next - s0;
     int64_t s = s0;
-    for (int64_t left = s1 > s0 ? s1 - s0 : 0; left != 0; --left, ++s, --to_next) {
+    // generator waves: step s + 1's draws during step s, and the same
+    // barriers as the compute waves, level changes included
+    if (HELP && helper) {
+        for (int64_t left = s1 > s0 ? s1 - s0 : 0; left != 0; --left, ++s, --to_next) {
+            if (to_next == 0) {
+                lvl = level_of(s, J.L, J.S);
+                s_next = next_level_step(lvl, J.L, J.S);
+                to_next = s_next - s;
+                hd = J.hdr[lvl];
+                if (stage) stage_brackets();
+            }
+            if (left != 1) produce(s + 1);
+            __syncthreads();
+        }
+    }
+    for (int64_t left = (HELP && helper) ? 0 : (s1 > s0 ? s1 - s0 : 0); left != 0;
+         --left, ++s, --to_next) {
         if (to_next == 0) {
             lvl = level_of(s, J.L, J.S);
             s_next = next_level_step(lvl, J.L, J.S);
@@ -425,14 +467,14 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             hd = J.hdr[lvl];
             if (stage) {
                 stage_brackets();
-                if (HELP && !helper && direct) lookup_q(rb, qv);
+                if (HELP && direct) lookup_q(rb, qv);
             }
         }
         const int par = (int)(s & 1);
         // per-step schedule: this step's temperature and band (loaded one
         // step ahead)
         double Tstep = 0.0;
-        if (perstep && !helper) {
+        if (perstep) {
             Tstep = st_next.T;
             hd.tmin = st_next.tmin;
             hd.tmax = st_next.tmax;
@@ -442,8 +484,29 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         uint32_t acc = 0;
         int c = 0, excl = 0, wtot = 0;
 
-        if (helper) {
-            if (left != 1) produce(s + 1);
+        if (fast) {
+            // 1-3a, narrow band with the decisions' table entries already read:
+            // with s = (1 - 2x) h the flip is accepted iff s - E_off <= thr[u]
+            // = tmin + q[u], i.e. s < q[u] + c with c = tmin + 1 + E_off.  As
+            // q <= tmax - tmin this one compare also decides the flips below
+            // and above the band.  |s| <= 2^30, E_off <= 2^30 and a direct
+            // level's |tmin| <= 256, so nothing here leaves int32.  The wave
+            // prefix of the accepted counts is the running sum of the lanes
+            // below in the F compare masks.
+            const int cc = hd.tmin + 1 + eoff;
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                // (h ^ mx) - mx = s, compared as (h ^ mx) < q + c + mx
+                const int mx = -(int)((xb >> f) & 1u);
+                const bool p = (h[f] ^ mx) < (int)qv[f] + cc + mx;
+                const uint64_t pm = ballot(p);
+                acc |= (uint32_t)p << f;
+                excl = __builtin_amdgcn_mbcnt_hi((uint32_t)(pm >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)pm, excl));
+                wtot += (int)__popcll(pm);
+            }
+            c = __popc(acc);
+            if (NW > 1) rec[par * RS + g] = acc | (xb << 8) | ((uint32_t)(excl + c) << 16);
         } else if (!idle) {
             // 1. cost of every flip and the draw-free decisions (branch-free).
             // Without direct tables the band tmin < d <= tmax is tested as one
@@ -548,28 +611,26 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             // 3a. accepted count, prefix over the wave; publish for the others
             c = __popc(acc);
             wave_prefix<CountBits<F>::value>(c, excl, wtot);
-            if (NW > 1) {
-                // record: accepted mask | x bits << 8 | inclusive prefix << 16
-                rec[par * NW * 64 + g] = acc | (xb << 8) | ((uint32_t)(excl + c) << 16);
-                if (lane == 0) tot[par * NW + wr] = wtot;
-            }
+            // record: accepted mask | x bits << 8 | inclusive prefix << 16
+            if (NW > 1) rec[par * RS + g] = acc | (xb << 8) | ((uint32_t)(excl + c) << 16);
         }
         if (sync) __syncthreads();
-        if (helper || idle) continue;
+        if (idle) continue;
 
         // 3b. the chosen flip.  Everything this step needs from LDS is read
         // in one straight-line group (clamped indices, no branches), so the
         // wave waits for LDS once.
+        // (on the last step these read draws no step uses: stale, in bounds)
         uint4 rbn[NB];
-        if (HELP) consume(left != 1 ? s + 1 : s, rbn);
+        if (HELP) consume(s + 1, rbn);
         const uint32_t vs = HELP ? vring[(int)(s & 3)] : 0u;
         int dEp = 0, tw = 0;
         uint32_t r4[4] = {0u, 0u, 0u, 0u};
         if (NW > 1) {
             dEp = dEs[par ^ 1];
-            const int twr = tot[par * NW + min(lane, NW - 1)];
+            const int twr = (int)(rec[par * RS + min(lane, NW - 1) * 64 + 63] >> 16);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) r4[q] = rec[par * NW * 64 + min(q, NW - 1) * 64 + lane];
+            for (int q = 0; q < 4; ++q) r4[q] = rec[par * RS + q * 64 + lane];
             tw = lane < NW ? twr : 0;
             // keep these reads together: left to itself the compiler sinks
             // the draw and record reads into the branches that use them, so
@@ -593,10 +654,12 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 bit = select_bit<F>(msk, rloc);
                 k = ts * F + bit;
                 xk = (readlane((int)xb, ts) >> bit) & 1;
-                int dsel = d[0];
+                // energy change (1 - 2 x_k) h_k of the chosen flip
+                int hsel = h[0];
 #pragma unroll
-                for (int f = 1; f < F; ++f) dsel = (bit == f) ? d[f] : dsel;
-                dk = readlane(dsel, ts);
+                for (int f = 1; f < F; ++f) hsel = (bit == f) ? h[f] : hsel;
+                const int hk = readlane(hsel, ts);
+                dk = xk ? -hk : hk;
             }
         } else {
             // wave totals sit in lanes 0..NW-1: a scan over 4 lanes suffices
@@ -618,11 +681,11 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 const int jw = j - (readlane(scan, ws) - readlane(tw, ws));
                 uint32_t r2;
                 if (NW <= 4) {
-                    r2 = r4[0];
-#pragma unroll
-                    for (int q = 1; q < 4; ++q) r2 = (ws == q) ? r4[q] : r2;
+                    const uint32_t r01 = (ws & 1) ? r4[1] : r4[0];
+                    const uint32_t r23 = (ws & 1) ? r4[3] : r4[2];
+                    r2 = (ws & 2) ? r23 : r01;
                 } else {
-                    r2 = rec[par * NW * 64 + ws * 64 + lane];
+                    r2 = rec[par * RS + ws * 64 + lane];
                 }
                 // first lane of wave ws whose inclusive prefix passes jw
                 const uint64_t bal = ballot((int)(r2 >> 16) > jw);
@@ -648,7 +711,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         }
         // the next step's direct-table decisions (its draws arrived with this
         // step's exchange); a level change re-reads them after staging
-        if (HELP && direct && left != 1) lookup_q(rbn, qv);
+        if (HELP && direct) lookup_q(rbn, qv);
         if (NW > 1 && pend) {
             // the previous step's energy change (written by its owner lane)
             E += (int64_t)__builtin_amdgcn_readfirstlane(dEp);
@@ -663,10 +726,10 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             const int delta = xk ? -1 : 1;
             const bool owner = g == (k / F);
             if (NW > 1 && owner) {
-                int dsel = d[0];
+                int hsel = h[0];
 #pragma unroll
-                for (int f = 1; f < F; ++f) dsel = (bit == f) ? d[f] : dsel;
-                dEs[par] = dsel + eoff;
+                for (int f = 1; f < F; ++f) hsel = (bit == f) ? h[f] : hsel;
+                dEs[par] = xk ? -hsel : hsel;   // (1 - 2 x_k) h_k
             }
             xb ^= owner ? (1u << (k % F)) : 0u;
             if (sparse) {
@@ -694,13 +757,15 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 for (int f = 0; f < F; ++f) h[f] += dv[f] * dw;
 #pragma unroll
                 for (int f = 0; f < F; ++f) dh[lane * F + f] = 0;
+            } else if (mul16) {
+                update_i16<WT, F>(raw, delta * wscale, h);
             } else if (mul24) {
                 // 8/16-bit couplings times a common factor below 2^23: each
-                // product is exact as a 24-bit multiply, which the compiler
-                // fuses with the add
+                // product is exact as a 24-bit multiply-add, done in place
                 const int dw = delta * wscale;
 #pragma unroll
-                for (int f = 0; f < F; ++f) h[f] = __mul24((int)raw[f], dw) + h[f];
+                for (int f = 0; f < F; ++f)
+                    asm("v_mad_i32_i24 %0, %1, %2, %0" : "+v"(h[f]) : "v"((int)raw[f]), "s"(dw));
             } else if (wscale == 1) {
                 // h + (+-raw): xor with the sign, add the sign's two's-complement fix
                 const int sx = delta > 0 ? 0 : -1;
@@ -712,7 +777,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             }
             ++nacc;
             if (NW == 1) {
-                E += (int64_t)dk + eoff;
+                E += (int64_t)dk;
                 const bool better = E < bE;
                 bE = better ? E : bE;
                 bxb = better ? xb : bxb;
@@ -1106,7 +1171,9 @@ template <typename WT, int F, bool TRACE, bool HELP>
 int launch_run_t(const JobDesc &J, const TraceDesc &T, int blocks, int threads, size_t lds,
                  void *stream) {
     const dim3 g(blocks), b(threads);
-    const bool wide = J.NW > 1 && !J.w_lds;
+    // (the wide variants take 16-bit couplings' factor as 16-bit too)
+    const bool wide = J.NW > 1 && !J.w_lds &&
+                      (sizeof(WT) != 2 || (J.wscale < (1 << 15) && J.wscale > -(1 << 15)));
     if (J.lvl_of_rep) {
         if (wide)
             hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, false, kModeWide>), g, b, lds,

@@ -134,7 +134,8 @@ void build_host_tables(const std::vector<double> &temps, HostTables &ht) {
         build_brackets(thr, ht.hdr[l], ht.brk);
         LevelHdr &hd = ht.hdr[l];
         if (L <= (size_t)kMaxDirectLevels && hd.tmax > hd.tmin &&
-            hd.tmax - hd.tmin <= kDirectSpan) {
+            hd.tmax - hd.tmin <= kDirectSpan && hd.tmin >= -kDirectTmin &&
+            hd.tmin <= kDirectTmin) {
             hd.q8 = nq++;
             for (int u = 0; u < 65536; ++u) ht.q8.push_back((uint8_t)(thr[u] - hd.tmin));
         }
