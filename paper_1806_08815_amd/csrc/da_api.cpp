@@ -600,7 +600,9 @@ LaunchShape tuned_shape(da_ctx *ctx, const LevelTables &lt, int32_t R, int64_t s
                 J.bE = scratch.bE;
                 J.eoff = scratch.eoff;
                 J.nacc = scratch.nacc;
-                J.s0 = steps / 3;
+                // a window inside the schedule: past its last step the level
+                // index would run off the level tables
+                J.s0 = std::min<int64_t>(steps / 3, steps - window);
                 J.s1 = J.s0 + window;
                 if (launch_state_zero(J, s) != 0) continue;
                 (void)hipEventRecord(a, s);

@@ -117,6 +117,20 @@ def test_direct_table_trace_parity(api, kind, N, dtype, F, rpw, rng):
     _same(gpu, ref, ("trace_k", "trace_E", "trace_eoff") + KEYS)
 
 
+@pytest.mark.parametrize("N,S,L", [(70, 100, 128), (90, 65, 128), (110, 300, 64), (130, 575, 128)])
+def test_tuned_short_schedules(api, N, S, L):
+    """Schedules of fewer than 576 steps: the tuner's timing window must stay
+    inside the schedule (past its last step the level index would leave the
+    level tables).  Each N is new to the process, so the tuner runs."""
+    Q = _q("random", N, 31)
+    ctx = api.da_create(Q)
+    sch = api.schedule(20.0, 1.0, "geometric", L, eoff_inc=2)
+    gpu = api.da_anneal(ctx, sch, 3, S, 9)
+    ref = oracle.anneal(Q, T_hi=20.0, T_lo=1.0, n_levels=L, eoff_inc=2, replicas=3, steps=S,
+                        seed=9)
+    _same(gpu, ref)
+
+
 @pytest.mark.parametrize("w_lds", [1, -1])
 def test_sk_bimodal_64_full(api, w_lds):
     """16 replicas x 10^4 steps of an N = 64 +-1 SK instance, escape offset on."""
