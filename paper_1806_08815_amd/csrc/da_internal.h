@@ -26,6 +26,8 @@ namespace dapt {
 // bucket D holds (lo, hi) = (ucut(last d of the bucket), ucut(first d)) packed
 // as lo | hi << 16, so u < lo accepts, u >= hi rejects, and only lo <= u < hi
 // needs the table entry thr[u].  With sh = 0 the bracket is exact (lo == hi).
+// The last bucket's lo is taken at its true end (0 once past tmax), and a
+// reject-all entry 0 follows the buckets of every level.
 //
 // Narrow bands (tmax - tmin <= kDirectSpan) also get a direct table of the
 // decision by draw: q[u] = thr[u] - tmin in [0, tmax - tmin], one byte per
@@ -45,7 +47,7 @@ constexpr int kDirectSpan = 255;
 constexpr int kDirectTmin = 256;
 constexpr int kMaxDirectLevels = 512;   // schedules with more levels use brackets only
 
-constexpr int kMaxBuckets = 4096;   // buckets per level
+constexpr int kMaxBuckets = 4096;   // bracket entries per level (reject-all included)
 constexpr int kMaxLevels = 4096;
 constexpr int kMaxN = 8192;
 constexpr int32_t kEoffMax = 1 << 30;

@@ -353,10 +353,15 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     LevelHdr hd = J.hdr[lvl];
     bool direct = false;   // this level decides in-band flips by its direct table
     bool fast = false;     // ... and this wave does so with one compare per flip
+    bool fastb = false;    // wide band: one bracket read per flip, no band tests
+    uint32_t ubmax = 0;    // first offset past the level's buckets
     auto stage_brackets = [&]() {
         __syncthreads();
         direct = has_q && hd.q8 >= 0;
         fast = dq && HELP && direct && full;
+        // (only in the variants without direct tables: carried beside the
+        // one-compare path, its code slows the narrow-band step)
+        fastb = !dq && HELP && full && !perstep && !single && hd.tmax < (1 << 29);
         if (direct) {
             const uint4 *src = reinterpret_cast<const uint4 *>(J.q8 + (size_t)hd.q8 * 65536);
             uint4 *dst = reinterpret_cast<uint4 *>(smem + w_bytes + kMaxBuckets * 4);
@@ -374,7 +379,9 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             }
         } else {
             const int nb = hd.tmax > hd.tmin ? ((hd.tmax - hd.tmin - 1) >> hd.sh) + 1 : 0;
-            for (int q = threadIdx.x; q < nb; q += blockDim.x) brk_l[q] = J.brk[hd.off + q];
+            ubmax = (uint32_t)nb << hd.sh;
+            // the buckets and the reject-all entry after them
+            for (int q = threadIdx.x; q <= nb; q += blockDim.x) brk_l[q] = J.brk[hd.off + q];
         }
         __syncthreads();
     };
@@ -506,6 +513,46 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 wtot += (int)__popcll(pm);
             }
             c = __popc(acc);
+            if (NW > 1) rec[par * RS + g] = acc | (xb << 8) | ((uint32_t)(excl + c) << 16);
+        } else if (fastb) {
+            // wide band with the draws at hand: one bracket read per flip and
+            // no band tests.  With s = (1 - 2x) h and C = tmin + 1 + E_off,
+            // s < C is below the band (accepted).  ub = s - C as an unsigned
+            // number indexes the buckets; offsets past them (above the band,
+            // and below it after the wrap) read the level's reject-all entry,
+            // and costs above tmax inside the last bucket meet its lower cut
+            // of 0, so the exact entry decides them.  tmax < 2^29 keeps C in
+            // int32.
+            const int C = hd.tmin + 1 + eoff;
+            int sv[F];
+            uint32_t u[F], e[F];
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                const int mx = -(int)((xb >> f) & 1u);
+                sv[f] = (h[f] ^ mx) - mx;
+                const uint32_t ub = (uint32_t)sv[f] - (uint32_t)C;
+                acc |= (uint32_t)(sv[f] < C) << f;
+                u[f] = draw16(rb, f);
+                e[f] = brk_l[min(ub, ubmax) >> hd.sh];
+            }
+            uint32_t fine = 0;
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                const uint32_t lo = e[f] & 0xFFFFu, hi = e[f] >> 16;
+                acc |= (uint32_t)(u[f] < lo) << f;
+                fine |= (uint32_t)((u[f] >= lo) & (u[f] < hi)) << f;
+            }
+            if (fine) {
+                const int32_t *thr = J.thr + (size_t)lvl * 65536;
+                int t[F];
+#pragma unroll
+                for (int f = 0; f < F; ++f) t[f] = thr[((fine >> f) & 1u) ? u[f] : 0u];
+#pragma unroll
+                for (int f = 0; f < F; ++f)
+                    acc |= (((fine >> f) & 1u) & (uint32_t)(sv[f] - eoff <= t[f])) << f;
+            }
+            c = __popc(acc);
+            wave_prefix<CountBits<F>::value>(c, excl, wtot);
             if (NW > 1) rec[par * RS + g] = acc | (xb << 8) | ((uint32_t)(excl + c) << 16);
         } else if (!idle) {
             // 1. cost of every flip and the draw-free decisions (branch-free).

@@ -65,19 +65,27 @@ void build_brackets(const int32_t *thr, LevelHdr &hd, std::vector<uint32_t> &brk
     hd.q8 = -1;
     hd.pad[0] = hd.pad[1] = hd.pad[2] = 0;
     hd.off = (int32_t)brk.size();
-    if (hd.tmax <= hd.tmin) return;   // no draw ever changes a decision
+    // every level ends with a reject-all entry (lo = hi = 0), which costs
+    // past the last bucket may read
+    if (hd.tmax <= hd.tmin) {   // no draw ever changes a decision
+        brk.push_back(0);
+        return;
+    }
     const int64_t range = (int64_t)hd.tmax - hd.tmin;
     int sh = 0;
-    while (((range + (int64_t(1) << sh) - 1) >> sh) > kMaxBuckets) ++sh;
+    while (((range + (int64_t(1) << sh) - 1) >> sh) > kMaxBuckets - 1) ++sh;
     const int64_t nb = (range + (int64_t(1) << sh) - 1) >> sh;
     for (int64_t D = 0; D < nb; ++D) {
+        // the lower cut at the bucket's true end: past tmax it is 0, so
+        // costs above the band that fall into the last bucket are decided
+        // by the exact table entry
         const int64_t ds = (int64_t)hd.tmin + 1 + (D << sh);
-        int64_t de = ds + (int64_t(1) << sh) - 1;
-        if (de > hd.tmax) de = hd.tmax;
+        const int64_t de = ds + (int64_t(1) << sh) - 1;
         const uint32_t lo = (uint32_t)ucut(thr, de);
         const uint32_t hi = (uint32_t)ucut(thr, ds);
         brk.push_back(lo | (hi << 16));
     }
+    brk.push_back(0);
     hd.sh = sh;
 }
 

@@ -117,6 +117,25 @@ def test_direct_table_trace_parity(api, kind, N, dtype, F, rpw, rng):
     _same(gpu, ref, ("trace_k", "trace_E", "trace_eoff") + KEYS)
 
 
+@pytest.mark.parametrize("N,dtype,F,rpw", [
+    (1024, 0, 8, 1), (1000, 0, 8, 1), (300, 4, 4, 2), (513, 0, 8, 1), (2048, 0, 8, 1), (64, 0, 4, 1),
+])
+def test_wide_band_trace_parity(api, N, dtype, F, rpw):
+    """Gaussian couplings with random-number waves: every level's band is wide
+    (buckets of 2^sh costs), so full waves decide each flip by one bracket read
+    (costs past the buckets meet the reject-all entry) and waves holding ghost
+    flips take the band tests; N = 1000, 300 and 513 mix both in one replica."""
+    Q = _q("gauss", N, 5)
+    T_hi, T_lo, inc = 3.0 * 2**16, 0.05 * 2**16, 2**16
+    R, S, L = 5, 1200, 6
+    ctx = api.da_create(Q, dtype)
+    sch = api.schedule(T_hi, T_lo, "geometric", L, eoff_inc=inc)
+    gpu = api.da_anneal_ex(ctx, sch, 3, R, S, 11, api.launch(F, rpw, 0, 1), trace=True)
+    ref = oracle.anneal(Q, T_hi=T_hi, T_lo=T_lo, n_levels=L, eoff_inc=inc, replica_base=3,
+                        replicas=R, steps=S, seed=11, trace=True)
+    _same(gpu, ref, ("trace_k", "trace_E", "trace_eoff") + KEYS)
+
+
 @pytest.mark.parametrize("N,S,L", [(70, 100, 128), (90, 65, 128), (110, 300, 64), (130, 575, 128)])
 def test_tuned_short_schedules(api, N, S, L):
     """Schedules of fewer than 576 steps: the tuner's timing window must stay
