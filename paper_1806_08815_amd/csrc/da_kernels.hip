@@ -12,13 +12,16 @@
 //     d > tmax rejects.  Only in-band flips pay for a Philox4x32-10 block (one
 //     block per 8 variables, so F <= 8 costs one call per lane) and an
 //     acceptance bracket; a global table read is needed only inside a
-//     non-exact bracket.  This reproduces d <= thr[u] exactly.
+//     non-exact bracket.  This reproduces d <= thr[u] exactly.  When draws
+//     come from generator waves, narrow bands take one compare per flip
+//     against a direct decision table, and wide bands one bracket read per
+//     flip with no band tests.
 //   * The accepted count and the rank of the chosen flip come from wave
-//     ballots of the bits of each lane's accepted count plus mbcnt (an
-//     exclusive prefix sum without data movement).  With NW > 1, lanes publish
-//     their masks, x bits and costs to LDS (double-buffered by step parity) and
-//     one workgroup barrier per step lets every wave find the chosen flip k on
-//     its own; nothing else is shared.
+//     ballots plus mbcnt (an exclusive prefix sum without data movement).
+//     With NW > 1, lanes publish their accepted masks, x bits and in-wave
+//     prefixes to LDS (double-buffered by step parity) and one workgroup
+//     barrier per step lets every wave find the chosen flip k on its own;
+//     nothing else is shared.
 //   * The only bulk traffic of a step is row k of W (N * dtype bytes), streamed
 //     once: every lane loads its F contiguous couplings with vector loads and
 //     updates its fields.  W stays in L2 / MALL / HBM, or in LDS when small.
@@ -206,8 +209,8 @@ size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk, int
 // (parallel tempering) every replica has its own level, read through L1/L2.
 //
 // Multi-wave replicas (NW > 1) exchange, once per step, each lane's accepted
-// mask and x bits plus each wave's accepted count through LDS, double-buffered
-// by step parity, around one workgroup barrier.  The energy change of the
+// mask, x bits and in-wave prefix (the last lane's is the wave's count)
+// through LDS, double-buffered by step parity, around one workgroup barrier.  The energy change of the
 // chosen flip is handed to the other waves one step later through the same
 // buffers (the owning lane writes it after the selection), so it never adds
 // an LDS round trip to the critical path; the energy and the best-state check
