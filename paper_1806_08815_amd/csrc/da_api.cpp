@@ -600,10 +600,7 @@ LaunchShape tuned_shape(da_ctx *ctx, const LevelTables &lt, int32_t R, int64_t s
                 J.bE = scratch.bE;
                 J.eoff = scratch.eoff;
                 J.nacc = scratch.nacc;
-                // a window inside the schedule: past its last step the level
-                // index would run off the level tables
-                J.s0 = std::min<int64_t>(steps / 3, steps - window);
-                J.s1 = J.s0 + window;
+                tune_window(steps, J.s0, J.s1);
                 if (launch_state_zero(J, s) != 0) continue;
                 (void)hipEventRecord(a, s);
                 const int e = launch_run(J, sh.F, sh.NH > 0, nullptr, sh.blocks, sh.threads, sh.lds, s);

@@ -46,6 +46,14 @@ std::shared_ptr<StepTables> get_step_tables(const da_schedule &s, int64_t S, std
 const double *device_neg_log_u(std::string &err);
 // Band header and brackets of one level from its threshold table.
 void build_brackets(const int32_t *thr, LevelHdr &hd, std::vector<uint32_t> &brk);
+// Steps [s0, s1) the autotuner times of an S-step schedule (S >= 1): up to 384
+// steps from about a third of the way in, never past the last step (beyond it
+// the level index would leave the level tables).
+inline void tune_window(int64_t S, int64_t &s0, int64_t &s1) {
+    const int64_t w = S < 384 ? S : 384;
+    s0 = S / 3 < S - w ? S / 3 : S - w;
+    s1 = s0 + w;
+}
 // Temperature of level l of a schedule.
 double schedule_temperature(const da_schedule &s, int l);
 // Host image of the tables of a temperature list.

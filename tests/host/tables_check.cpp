@@ -1,0 +1,127 @@
+// Host checks of the library's level tables against the way the step kernel
+// uses them: every level's bucket count fits the LDS staging area and its
+// reject-all entry sits where staging and the one-read form look for it; the
+// three in-kernel decision forms (band tests + bracket, one bracket read per
+// flip, direct table) agree with the definition d <= thr[u] of the Metropolis
+// test as a threshold on the 16-bit draw; and the autotuner's timing window
+// stays inside its schedule.  Exit status 0 when every check holds.
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <random>
+#include <vector>
+
+#include "da_internal.h"
+#include "da_runtime.h"
+
+using namespace dapt;
+
+static long g_bad = 0;
+#define CHECK(c, ...)                    \
+    do {                                 \
+        if (!(c)) {                      \
+            if (g_bad < 20) {            \
+                std::printf(__VA_ARGS__); \
+                std::printf("\n");       \
+            }                            \
+            ++g_bad;                     \
+        }                                \
+    } while (0)
+
+// band tests, then the bracket of an in-band cost, then the exact entry
+static bool band_form(const int32_t *thr, const LevelHdr &hd, const uint32_t *brk, int64_t d,
+                      uint32_t u) {
+    const int64_t t1 = (int64_t)hd.tmin + 1, span = (int64_t)hd.tmax - hd.tmin;
+    if (d < t1) return true;
+    const int64_t ub = d - t1;
+    if (ub >= span) return false;
+    const uint32_t e = brk[hd.off + (ub >> hd.sh)];
+    const uint32_t lo = e & 0xFFFFu, hi = e >> 16;
+    if (u < lo) return true;
+    if (u >= hi) return false;
+    return d <= thr[u];
+}
+
+// one bracket read, no band tests: the offset wraps as a 32-bit unsigned
+// number and is clamped to the first offset past the buckets
+static bool one_read_form(const int32_t *thr, const LevelHdr &hd, const uint32_t *brk, int64_t d,
+                          uint32_t u) {
+    const int64_t t1 = (int64_t)hd.tmin + 1;
+    const int nb = hd.tmax > hd.tmin ? ((hd.tmax - hd.tmin - 1) >> hd.sh) + 1 : 0;
+    const uint32_t ubmax = (uint32_t)nb << hd.sh;
+    const uint32_t ub = (uint32_t)(uint64_t)(d - t1);
+    const uint32_t idx = (ub < ubmax ? ub : ubmax) >> hd.sh;
+    bool acc = d < t1;
+    const uint32_t e = brk[hd.off + idx];
+    const uint32_t lo = e & 0xFFFFu, hi = e >> 16;
+    acc = acc || u < lo;
+    if (u >= lo && u < hi) acc = acc || d <= thr[u];
+    return acc;
+}
+
+int main() {
+    std::vector<std::vector<double>> lists;
+    for (double Thi : {0.3, 3.0, 20.0, 60.0, 196608.0, 1e6, 3e8, 5e9})
+        for (int L : {1, 6, 64})
+            for (double ratio : {1.0, 0.05}) {
+                std::vector<double> t;
+                for (int l = 0; l < L; ++l)
+                    t.push_back(L == 1 ? Thi : Thi * std::pow(ratio, (double)l / (L - 1)));
+                lists.push_back(t);
+            }
+    lists.push_back({0.0});
+    std::mt19937_64 rng(12345);
+    long levels = 0, decisions = 0;
+    for (const auto &t : lists) {
+        HostTables ht;
+        build_host_tables(t, ht);
+        int nq = 0;
+        for (size_t l = 0; l < t.size(); ++l) {
+            const LevelHdr &hd = ht.hdr[l];
+            const int32_t *thr = ht.thr.data() + l * 65536;
+            const uint32_t *brk = ht.brk.data();
+            ++levels;
+            CHECK(hd.tmin == thr[65535] && hd.tmax == thr[0], "T=%g: band limits", t[l]);
+            const int nb = hd.tmax > hd.tmin ? ((hd.tmax - hd.tmin - 1) >> hd.sh) + 1 : 0;
+            CHECK(nb + 1 <= kMaxBuckets, "T=%g: %d buckets", t[l], nb);
+            CHECK((size_t)hd.off + nb < ht.brk.size() && brk[hd.off + nb] == 0,
+                  "T=%g: reject-all entry missing", t[l]);
+            const bool narrow = hd.tmax > hd.tmin && hd.tmax - hd.tmin <= kDirectSpan &&
+                                hd.tmin >= -kDirectTmin && hd.tmin <= kDirectTmin &&
+                                t.size() <= (size_t)kMaxDirectLevels;
+            CHECK(narrow == (hd.q8 >= 0), "T=%g: direct table %d", t[l], hd.q8);
+            const uint8_t *q = hd.q8 >= 0 ? ht.q8.data() + (size_t)hd.q8 * 65536 : nullptr;
+            if (hd.q8 >= 0) CHECK(hd.q8 == nq++, "T=%g: direct table order", t[l]);
+            // costs across and beyond the band, and the extremes of the int32 range
+            std::vector<int64_t> ds = {INT32_MIN, -(int64_t(1) << 30), -1, 0, 1, int64_t(1) << 30};
+            for (int64_t k = -300; k <= 300; ++k) {
+                ds.push_back((int64_t)hd.tmin + k);
+                ds.push_back((int64_t)hd.tmax + k);
+            }
+            std::uniform_int_distribution<int64_t> band((int64_t)hd.tmin - 5, (int64_t)hd.tmax + 5);
+            for (int k = 0; k < 600; ++k) ds.push_back(band(rng));
+            for (int64_t d : ds)
+                for (int k = 0; k < 6; ++k) {
+                    const uint32_t u = k == 0 ? 0u : (k == 1 ? 65535u : (uint32_t)(rng() & 0xFFFFu));
+                    const bool want = d <= thr[u];
+                    ++decisions;
+                    CHECK(band_form(thr, hd, brk, d, u) == want, "T=%g d=%lld u=%u: band form",
+                          t[l], (long long)d, u);
+                    if (hd.tmax < (1 << 29))
+                        CHECK(one_read_form(thr, hd, brk, d, u) == want,
+                              "T=%g d=%lld u=%u: one-read form", t[l], (long long)d, u);
+                    if (q && d >= -(int64_t(1) << 30) - (int64_t(1) << 30) + 512)
+                        CHECK(((d - ((int64_t)hd.tmin + 1)) < (int64_t)q[u]) == want,
+                              "T=%g d=%lld u=%u: direct table", t[l], (long long)d, u);
+                }
+        }
+    }
+    for (int64_t S = 1; S <= 5000; ++S) {
+        int64_t s0 = 0, s1 = 0;
+        tune_window(S, s0, s1);
+        CHECK(s0 >= 0 && s1 <= S && s1 - s0 == (S < 384 ? S : 384), "tune window S=%lld",
+              (long long)S);
+    }
+    std::printf("levels %ld decisions %ld failures %ld\n", levels, decisions, g_bad);
+    return g_bad != 0;
+}
