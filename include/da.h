@@ -333,6 +333,10 @@ const char *da_last_error(const da_ctx *ctx);
 /* Static description of a status code. */
 const char *da_strerror(int status);
 
+/* Identity of this build: the SHA-256 (hex) of the library sources it was
+ * compiled from, so a caller can refuse a binary older than its sources. */
+const char *da_build_id(void);
+
 /* Host-only: the 65536-entry Metropolis threshold table at temperature T
  * (thr[u] = ceil(-T ln((u + 1/2)/65536)) - 1 clamped to [-1, 2^30]; all -1
  * for T <= 0) and the temperature of level l of a schedule.  These are what

@@ -83,6 +83,11 @@ def lib() -> ctypes.CDLL:
         L.orc_pt.argtypes = [ctypes.c_int, P, P, ctypes.c_int, ctypes.c_int, i64, ctypes.c_int,
                              i64, u64, P, P, P, P, P, P, P]
         L.orc_pt.restype = ctypes.c_int
+        L.orc_pt_ex.argtypes = [ctypes.c_int, P, P, ctypes.c_int, i64, ctypes.c_int, i64,
+                                ctypes.c_int, i64, u64, P, P, P, P, P, P, P, P, P]
+        L.orc_pt_ex.restype = ctypes.c_int
+        L.orc_pt_sweep.argtypes = [ctypes.c_int, P, P, P, P, u64, u32, u32, P]
+        L.orc_pt_sweep.restype = i64
         L.orc_rep_new.argtypes = [ctypes.c_int, P, ctypes.c_int, u64, u32]
         L.orc_rep_new.restype = P
         L.orc_rep_step.argtypes = [P, P, u64, u32, u32, i64]
@@ -200,26 +205,56 @@ def anneal(Q, *, T_hi: float, T_lo: float, kind: int = SCHED_GEOMETRIC, n_levels
 
 
 def pt(Q, temps, *, chains: int, rounds: int, steps_per_round: int, eoff_inc: int = 0,
-       seed: int = 1) -> dict:
+       seed: int = 1, chain_base: int = 0, slot_trace: bool = False) -> dict:
+    """Parallel tempering of chains chain_base .. chain_base+chains-1 (outputs
+    indexed from the first of them).  pair_swaps [chains][M-1] are the accepted
+    exchanges per pair; with slot_trace, slot_trace [chains][rounds][M] holds
+    every replica's slot after each round's exchange sweep."""
     Q = _q(Q)
     N = Q.shape[0]
     t = np.ascontiguousarray(np.asarray(temps, dtype=np.float64))
     M = t.shape[0]
-    R = M * int(chains)
+    C = int(chains)
+    R = M * C
     out = {
         "best_x": np.zeros((R, N), np.uint8), "best_E": np.zeros(R, np.int64),
         "final_x": np.zeros((R, N), np.uint8), "final_E": np.zeros(R, np.int64),
         "n_accept": np.zeros(R, np.int64), "slot": np.zeros(R, np.int32),
-        "n_swaps": np.zeros(int(chains), np.int64),
+        "n_swaps": np.zeros(C, np.int64),
+        "pair_swaps": np.zeros((C, max(M - 1, 1)), np.int64),
     }
-    rc = lib().orc_pt(N, _p(Q), _p(t), M, int(chains), int(rounds), int(steps_per_round),
-                      int(eoff_inc), ctypes.c_uint64(seed),
-                      _p(out["best_x"]), _p(out["best_E"]), _p(out["final_x"]),
-                      _p(out["final_E"]), _p(out["n_accept"]), _p(out["slot"]),
-                      _p(out["n_swaps"]))
+    tr = np.zeros((C, int(rounds), M), np.int32) if slot_trace else None
+    rc = lib().orc_pt_ex(N, _p(Q), _p(t), M, int(chain_base), C, int(rounds),
+                         int(steps_per_round), int(eoff_inc), ctypes.c_uint64(seed),
+                         _p(out["best_x"]), _p(out["best_E"]), _p(out["final_x"]),
+                         _p(out["final_E"]), _p(out["n_accept"]), _p(out["slot"]),
+                         _p(out["n_swaps"]), _p(tr), _p(out["pair_swaps"]))
     if rc != 0:
         raise ValueError("oracle pt rejected its arguments")
+    out["pair_swaps"] = out["pair_swaps"][:, :max(M - 1, 0)]
+    if slot_trace:
+        out["slot_trace"] = tr
     return out
+
+
+_lnU = None
+
+
+def pt_sweep(E, temps, replica_in_slot, seed: int, chain: int, round_: int):
+    """One exchange sweep over the ladder (frozen energies E of the chain's
+    replicas); returns (new replica_in_slot, accepted swaps per pair)."""
+    global _lnU
+    E = np.ascontiguousarray(np.asarray(E, dtype=np.int64))
+    t = np.ascontiguousarray(np.asarray(temps, dtype=np.float64))
+    M = t.shape[0]
+    if _lnU is None:
+        _lnU = np.log((np.arange(65536, dtype=np.float64) + 0.5) / 65536.0)
+    lnU = _lnU
+    ris = np.ascontiguousarray(np.asarray(replica_in_slot, dtype=np.int32)).copy()
+    ps = np.zeros(max(M - 1, 1), np.int64)
+    lib().orc_pt_sweep(M, _p(E), _p(t), _p(lnU), _p(ris), ctypes.c_uint64(seed), int(chain),
+                       int(round_), _p(ps))
+    return ris, ps[:max(M - 1, 0)]
 
 
 class Replica:

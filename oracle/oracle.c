@@ -364,26 +364,59 @@ int orc_anneal(int N, const int32_t *Q, double T_hi, double T_lo, int kind, int 
 /* probability min(1, exp((1/T_p - 1/T_{p+1}) (E_a - E_b))), tested as       */
 /* ln U_u < (1/T_p - 1/T_{p+1}) * (E_a - E_b) with U_u = (u + 1/2)/65536.    */
 /* ------------------------------------------------------------------------ */
-int orc_pt(int N, const int32_t *Q, const double *temps, int M, int chains,
-           int64_t rounds, int K, int64_t eoff_inc, uint64_t seed,
-           uint8_t *best_x, int64_t *best_E, uint8_t *final_x, int64_t *final_E,
-           int64_t *n_acc, int32_t *slot_of_replica, int64_t *n_swaps)
+/* One exchange sweep of a chain (the exchange move of Algorithm 3): for
+ * p = 0 .. M-2 in ascending order, the replicas a, b now in slots p and p+1
+ * (after any swap made earlier in the same sweep) exchange temperatures with
+ * probability min(1, exp((1/T_p - 1/T_{p+1}) (E_a - E_b))), tested as
+ * ln U_u < (1/T_p - 1/T_{p+1}) (E_a - E_b), u the 16-bit exchange draw of
+ * (chain c, round t, pair p).  E[q] is the energy of the chain's replica q;
+ * replica_in_slot is updated in place; accepted swaps of pair p are added to
+ * pair_swaps[p] when it is given.  Returns the number of accepted swaps. */
+int64_t orc_pt_sweep(int M, const int64_t *E, const double *temps, const double *lnU,
+                     int *replica_in_slot, uint64_t seed, uint32_t c, uint32_t t,
+                     int64_t *pair_swaps)
 {
-    if (N < 1 || M < 1 || chains < 0 || rounds < 0 || K < 0) return -1;
+    int64_t swaps = 0;
+    for (int p = 0; p + 1 < M; ++p) {
+        int a = replica_in_slot[p], bq = replica_in_slot[p + 1];
+        double dbeta = 1.0 / temps[p] - 1.0 / temps[p + 1];
+        double delta = dbeta * (double)(E[a] - E[bq]);
+        uint32_t u = orc_exchange_draw(seed, c, t, (uint32_t)p);
+        if (lnU[u] < delta) {
+            replica_in_slot[p] = bq;
+            replica_in_slot[p + 1] = a;
+            ++swaps;
+            if (pair_swaps) pair_swaps[p] += 1;
+        }
+    }
+    return swaps;
+}
+
+/* Parallel tempering of chains chain_base .. chain_base+chains-1 (outputs
+ * indexed from 0 for the first of them).  Optional extra outputs:
+ * slot_trace [chains][rounds][M], the slot of each replica after every
+ * round's exchange sweep; pair_swaps [chains][M-1], accepted swaps per pair. */
+int orc_pt_ex(int N, const int32_t *Q, const double *temps, int M, int64_t chain_base,
+              int chains, int64_t rounds, int K, int64_t eoff_inc, uint64_t seed,
+              uint8_t *best_x, int64_t *best_E, uint8_t *final_x, int64_t *final_E,
+              int64_t *n_acc, int32_t *slot_of_replica, int64_t *n_swaps,
+              int32_t *slot_trace, int64_t *pair_swaps)
+{
+    if (N < 1 || M < 1 || chains < 0 || rounds < 0 || K < 0 || chain_base < 0) return -1;
     for (int p = 0; p < M; ++p) {
         if (!(temps[p] > 0.0)) return -1;
         if (p + 1 < M && !(temps[p] < temps[p + 1])) return -1;
     }
-    int R = M * chains;
     int64_t *W = malloc(sizeof(int64_t) * (size_t)N * N);
     int64_t *b = malloc(sizeof(int64_t) * (size_t)N);
     int32_t *thr = malloc(sizeof(int32_t) * (size_t)M * 65536);
     double *lnU = malloc(sizeof(double) * 65536);
     uint8_t *scratch = malloc((size_t)N);
-    orc_rep *reps = calloc((size_t)(R > 0 ? R : 1), sizeof(orc_rep));
-    int *replica_in_slot = malloc(sizeof(int) * (size_t)(M > 0 ? M : 1));
-    int fail = !W || !b || !thr || !lnU || !scratch || !reps || !replica_in_slot;
-    for (int q = 0; q < R && !fail; ++q) {
+    orc_rep *reps = calloc((size_t)M, sizeof(orc_rep));
+    int64_t *E = malloc(sizeof(int64_t) * (size_t)M);
+    int *replica_in_slot = malloc(sizeof(int) * (size_t)M);
+    int fail = !W || !b || !thr || !lnU || !scratch || !reps || !E || !replica_in_slot;
+    for (int q = 0; q < M && !fail; ++q) {
         reps[q].N = N;
         reps[q].x = malloc((size_t)N);
         reps[q].best_x = malloc((size_t)N);
@@ -394,53 +427,59 @@ int orc_pt(int N, const int32_t *Q, const double *temps, int M, int chains,
         orc_derive(N, Q, W, b);
         for (int p = 0; p < M; ++p) orc_threshold_table(temps[p], thr + (size_t)p * 65536);
         for (int u = 0; u < 65536; ++u) lnU[u] = log(((double)u + 0.5) / 65536.0);
-        for (int c = 0; c < chains; ++c) {
+        for (int cc = 0; cc < chains; ++cc) {
+            const uint32_t c = (uint32_t)(chain_base + cc);
+            /* replica m of chain c has id c*M + m and starts in slot m */
             for (int m = 0; m < M; ++m) {
-                orc_rep *st = &reps[c * M + m];
-                orc_init_state(st, W, b, ORC_INIT_RANDOM, seed, (uint32_t)(c * M + m));
+                orc_init_state(&reps[m], W, b, ORC_INIT_RANDOM, seed, c * (uint32_t)M + (uint32_t)m);
                 replica_in_slot[m] = m;
             }
             int64_t swaps = 0;
             for (int64_t t = 0; t < rounds; ++t) {
+                /* K DA steps in every replica at the temperature of its slot */
                 for (int p = 0; p < M; ++p) {
                     int q = replica_in_slot[p];
-                    orc_rep *st = &reps[c * M + q];
                     for (int i = 0; i < K; ++i) {
                         uint32_t s = (uint32_t)(t * K + i);
-                        orc_step(st, W, thr + (size_t)p * 65536, seed, (uint32_t)(c * M + q), s,
-                                 eoff_inc, scratch);
+                        orc_step(&reps[q], W, thr + (size_t)p * 65536, seed,
+                                 c * (uint32_t)M + (uint32_t)q, s, eoff_inc, scratch);
                     }
                 }
-                for (int p = 0; p + 1 < M; ++p) {
-                    int a = replica_in_slot[p], bq = replica_in_slot[p + 1];
-                    double dbeta = 1.0 / temps[p] - 1.0 / temps[p + 1];
-                    double delta = dbeta * (double)(reps[c * M + a].E - reps[c * M + bq].E);
-                    uint32_t u = orc_exchange_draw(seed, (uint32_t)c, (uint32_t)t, (uint32_t)p);
-                    if (lnU[u] < delta) {
-                        replica_in_slot[p] = bq;
-                        replica_in_slot[p + 1] = a;
-                        ++swaps;
-                    }
-                }
+                for (int q = 0; q < M; ++q) E[q] = reps[q].E;
+                swaps += orc_pt_sweep(M, E, temps, lnU, replica_in_slot, seed, c, (uint32_t)t,
+                                      pair_swaps ? pair_swaps + (size_t)cc * (M - 1) : NULL);
+                if (slot_trace)
+                    for (int p = 0; p < M; ++p)
+                        slot_trace[((size_t)cc * rounds + t) * M + replica_in_slot[p]] = p;
             }
             for (int m = 0; m < M; ++m) {
-                int q = c * M + m;
-                if (best_x) memcpy(best_x + (size_t)q * N, reps[q].best_x, (size_t)N);
-                if (final_x) memcpy(final_x + (size_t)q * N, reps[q].x, (size_t)N);
-                if (best_E) best_E[q] = reps[q].best_E;
-                if (final_E) final_E[q] = reps[q].E;
-                if (n_acc) n_acc[q] = reps[q].n_acc;
+                size_t q = (size_t)cc * M + m;
+                if (best_x) memcpy(best_x + q * N, reps[m].best_x, (size_t)N);
+                if (final_x) memcpy(final_x + q * N, reps[m].x, (size_t)N);
+                if (best_E) best_E[q] = reps[m].best_E;
+                if (final_E) final_E[q] = reps[m].E;
+                if (n_acc) n_acc[q] = reps[m].n_acc;
             }
             if (slot_of_replica)
-                for (int p = 0; p < M; ++p) slot_of_replica[c * M + replica_in_slot[p]] = p;
-            if (n_swaps) n_swaps[c] = swaps;
+                for (int p = 0; p < M; ++p) slot_of_replica[(size_t)cc * M + replica_in_slot[p]] = p;
+            if (n_swaps) n_swaps[cc] = swaps;
         }
     }
-    for (int q = 0; q < R && reps; ++q) {
+    for (int q = 0; q < M && reps; ++q) {
         free(reps[q].x); free(reps[q].best_x); free(reps[q].h);
     }
-    free(W); free(b); free(thr); free(lnU); free(scratch); free(reps); free(replica_in_slot);
+    free(W); free(b); free(thr); free(lnU); free(scratch); free(reps); free(E);
+    free(replica_in_slot);
     return fail ? -1 : 0;
+}
+
+int orc_pt(int N, const int32_t *Q, const double *temps, int M, int chains,
+           int64_t rounds, int K, int64_t eoff_inc, uint64_t seed,
+           uint8_t *best_x, int64_t *best_E, uint8_t *final_x, int64_t *final_E,
+           int64_t *n_acc, int32_t *slot_of_replica, int64_t *n_swaps)
+{
+    return orc_pt_ex(N, Q, temps, M, 0, chains, rounds, K, eoff_inc, seed, best_x, best_E,
+                     final_x, final_E, n_acc, slot_of_replica, n_swaps, NULL, NULL);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -104,6 +104,15 @@ def lib() -> ctypes.CDLL:
     # first makes libdapt.so bind to that one copy instead of a second runtime.
     import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
+    # a library built from other sources than these is refused, not run
+    from . import build as _build
+    L.da_build_id.restype = ctypes.c_char_p
+    L.da_build_id.argtypes = []
+    built, here = L.da_build_id().decode(), _build.source_hash()
+    if built != here:
+        raise ImportError(f"{LIB_PATH} was built from other sources (build id {built[:12]}, "
+                          f"sources {here[:12]}): rebuild it with "
+                          "`python -m paper_1806_08815_amd.build`")
     sig = {
         "da_create": (_i32, [_P, _i32, _i32, ctypes.POINTER(_P)]),
         "da_destroy": (None, [_P]),

@@ -20,6 +20,21 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdapt.so")
 SOURCES = ["da_kernels.hip", "da_probe.hip", "da_tables.cpp", "da_api.cpp", "da_server.cpp"]
+HEADERS = ["da_internal.h", "da_runtime.h"]
+
+
+def source_hash() -> str:
+    """SHA-256 over the library's sources and headers (and include/da.h), in a
+    fixed order.  The built library reports the hash it was built from
+    (da_build_id), so a binary older than its sources is detected at load."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in SOURCES + HEADERS:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    with open(os.path.join(INCLUDE, "da.h"), "rb") as f:
+        h.update(b"da.h\0" + f.read())
+    return h.hexdigest()
 
 
 def hipcc() -> str:
@@ -36,9 +51,12 @@ def build_library(verbose: bool = False) -> str:
     common = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-ffp-contract=off",
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
               "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
+    build_id = source_hash()
     for src in SOURCES:
         obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
         cmd = [hipcc(), *common, "-c", os.path.join(CSRC, src), "-o", obj]
+        if src == "da_api.cpp":
+            cmd.insert(1, f'-DDAPT_BUILD_ID="{build_id}"')
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -121,12 +122,7 @@ LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch,
                          bool anneal_mode, bool direct) {
     LaunchShape sh;
     const int stage = anneal_mode ? 1 : 0;
-    int cus = 256;
-    {
-        int dev = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    }
+    const int cus = ctx->cus;
     // Few replicas per CU: each replica's step latency is the limit, so spread
     // a replica over more waves (4 variables per lane) and move the random
     // numbers to their own waves.  A full chip is limited by total work: 8
@@ -202,7 +198,8 @@ JobDesc make_job(const da_ctx *ctx, const LevelTables &lt, int32_t R, uint32_t r
     J.s1 = steps;
     J.S = steps;
     J.L = lt.L;
-    J.eoff_inc = s.eoff_inc;
+    // increments above 2^30 act as 2^30: the offset saturates there at once
+    J.eoff_inc = std::min<int32_t>(s.eoff_inc, kEoffMax);
     J.single = s.trial == DA_TRIAL_SINGLE ? 1 : 0;
     J.ell = ctx->d_ell;
     J.ell_D = ctx->ell_D;
@@ -263,9 +260,13 @@ void append_batch_items(const JobDesc &J, int job_index, std::vector<BatchItem> 
 
 int BatchRunner::prepare(std::string &err) {
     if (exec[0] && exec[1]) return DA_OK;
-    int dev = 0, cus = 256;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int dev = 0, cus = 0;
+    hipError_t qe = hipGetDevice(&dev);
+    if (qe == hipSuccess) qe = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (qe != hipSuccess || cus < 1) {
+        err = std::string("batch runner: device query failed: ") + hipGetErrorString(qe);
+        return DA_EDEVICE;
+    }
     blocks = cus;
     lds = 0;
     // room for any job, sparse row lists' delta buffers included
@@ -498,10 +499,13 @@ int create_ctx(const HostMatrix &hm, hipStream_t s, da_ctx **out, std::string &e
     ctx->ld = hm.ld;
     ctx->dtype = hm.dtype;
     ctx->wscale = hm.wscale;
-    (void)hipGetDevice(&ctx->device);
     const char *what = nullptr;
-    hipError_t e = hipMalloc(&ctx->d_W, hm.W.size());
-    if (e != hipSuccess) what = "W allocation";
+    hipError_t e = hipGetDevice(&ctx->device);
+    if (e != hipSuccess) what = "device query";
+    if (!what && (e = hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount,
+                                            ctx->device)) != hipSuccess)
+        what = "compute-unit count";
+    if (!what && (e = hipMalloc(&ctx->d_W, hm.W.size())) != hipSuccess) what = "W allocation";
     if (!what && (e = hipMalloc(&ctx->d_b, hm.b.size() * 4)) != hipSuccess) what = "b allocation";
     if (!what && (e = hipMemcpyAsync(ctx->d_W, hm.W.data(), hm.W.size(), hipMemcpyHostToDevice,
                                      s)) != hipSuccess)
@@ -561,72 +565,84 @@ static bool want_direct(const LevelTables &lt, const da_schedule &sched, int64_t
     return lt.d_q8 != nullptr && sched.n_levels > 0 && steps >= 256 * (int64_t)sched.n_levels;
 }
 
-LaunchShape tuned_shape(da_ctx *ctx, const LevelTables &lt, int32_t R, int64_t steps,
-                        const da_schedule &sched, hipStream_t s) {
+int tuned_shape(da_ctx *ctx, const LevelTables &lt, int32_t R, int64_t steps,
+                const da_schedule &sched, hipStream_t s, bool may_time, LaunchShape &out) {
     const bool direct = want_direct(lt, sched, steps);
     int dev = 0;
-    (void)hipGetDevice(&dev);
+    int rc = check_hip(ctx, hipGetDevice(&dev), "autotuner: device query");
+    if (rc) return rc;
     int rb = 1;
     while (rb < R) rb <<= 1;
     const TuneKey key{dev, ctx->N, ctx->dtype, rb};
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         auto it = g_tune.find(key);
-        if (it != g_tune.end()) return choose_shape(ctx, R, &it->second, true, direct);
+        if (it != g_tune.end()) {
+            out = choose_shape(ctx, R, &it->second, true, direct);
+            return DA_OK;
+        }
     }
     const int64_t window = std::min<int64_t>(steps, 384);
-    if (window < 64) return choose_shape(ctx, R, nullptr, true, direct);
-    StateBuf scratch;
-    std::string err;
-    if (!scratch.ensure(R, ctx->ld, err)) return choose_shape(ctx, R, nullptr, true, direct);
+    out = choose_shape(ctx, R, nullptr, true, direct);
+    if (window < 64 || !may_time) return DA_OK;
+    // The candidates run on the context's own replica state (it must hold R
+    // replicas already); the caller initialises it for the real run afterwards.
+    if (ctx->st.cap < R || ctx->st.ld != ctx->ld)
+        return fail(ctx, DA_EINVAL, "autotuner: replica state not allocated");
     hipEvent_t a = nullptr, b = nullptr;
-    (void)hipEventCreate(&a);
-    (void)hipEventCreate(&b);
+    rc = check_hip(ctx, hipEventCreate(&a), "autotuner: event create");
+    if (!rc) rc = check_hip(ctx, hipEventCreate(&b), "autotuner: event create");
     da_launch best{0, 0, 0, 0};
     float best_ms = 1e30f;
     for (int F : {4, 8}) {
         for (int rpw : {1, 2, 4}) {
             for (int rng : {1, -1}) {
+                if (rc) break;
                 const da_launch cand{F, rpw, 0, rng};
                 const LaunchShape sh = choose_shape(ctx, R, &cand, true, direct);
                 if (sh.RPW != rpw || sh.F != F || sh.threads > 1024 ||
                     sh.lds > (size_t)device_lds_limit())
                     continue;
                 JobDesc J = make_job(ctx, lt, R, 0u, 1u, steps, sched, sh);
-                J.h = scratch.h;
-                J.x = scratch.x;
-                J.bx = scratch.bx;
-                J.E = scratch.E;
-                J.bE = scratch.bE;
-                J.eoff = scratch.eoff;
-                J.nacc = scratch.nacc;
                 tune_window(steps, J.s0, J.s1);
-                if (launch_state_zero(J, s) != 0) continue;
-                (void)hipEventRecord(a, s);
-                const int e = launch_run(J, sh.F, sh.NH > 0, nullptr, sh.blocks, sh.threads, sh.lds, s);
-                (void)hipEventRecord(b, s);
-                if (e != 0 || hipEventSynchronize(b) != hipSuccess) {
-                    (void)hipGetLastError();
-                    continue;
+                if (const char *why = job_range_error(J)) {
+                    rc = fail(ctx, DA_EINVAL, std::string("autotuner: ") + why);
+                    break;
                 }
+                // any failure here is a device fault or a launch the device
+                // refused: report it with the candidate instead of moving on
+                char what[160];
+                std::snprintf(what, sizeof what,
+                              "autotuner candidate (flips/lane %d, replicas/workgroup %d, "
+                              "rng waves %d)", F, rpw, rng);
+                rc = check_hip(ctx, (hipError_t)launch_state_zero(J, s), what);
+                if (!rc) rc = check_hip(ctx, hipEventRecord(a, s), what);
+                if (!rc)
+                    rc = check_hip(ctx,
+                                   (hipError_t)launch_run(J, sh.F, sh.NH > 0, nullptr, sh.blocks,
+                                                          sh.threads, sh.lds, s),
+                                   what);
+                if (!rc) rc = check_hip(ctx, hipEventRecord(b, s), what);
+                if (!rc) rc = check_hip(ctx, hipEventSynchronize(b), what);
                 float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, a, b);
-                if (ms < best_ms) {
+                if (!rc) rc = check_hip(ctx, hipEventElapsedTime(&ms, a, b), what);
+                if (!rc && ms < best_ms) {
                     best_ms = ms;
                     best = cand;
                 }
             }
         }
     }
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
-    scratch.release();
-    if (best.flips_per_lane == 0) return choose_shape(ctx, R, nullptr, true, direct);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (rc) return rc;
+    if (best.flips_per_lane == 0) return DA_OK;
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         g_tune[key] = best;
     }
-    return choose_shape(ctx, R, &best, true, direct);
+    out = choose_shape(ctx, R, &best, true, direct);
+    return DA_OK;
 }
 
 int next_events(da_ctx *ctx, hipEvent_t &e0, hipEvent_t &e1) {
@@ -791,16 +807,24 @@ int enqueue_anneal(da_ctx *ctx, const da_schedule *schedule, int64_t replica_bas
     ctx->keep_steps = jt.steps;
     if (!ctx->st.ensure(replicas, ctx->ld, err)) return fail(ctx, DA_ENOMEM, err);
     const LevelTables &lt0 = *jt.levels;
-    const LaunchShape sh =
-        (launch == nullptr && trace_dev == nullptr && tune_enabled() && !jt.steps)
-            ? tuned_shape(ctx, lt0, replicas, steps, *schedule, s)
-            : choose_shape(ctx, replicas, launch, true, !jt.steps && want_direct(lt0, *schedule, steps));
+    // from here on the state changes: it is resumable again only on success
+    ctx->st_step = -1;
+    LaunchShape sh;
+    // the tuner times its candidates on the replica state, so only when the
+    // run starts from the initial state (which is written after it); a resumed
+    // piece takes the cached choice or the default
+    if (launch == nullptr && trace_dev == nullptr && tune_enabled() && !jt.steps) {
+        rc = tuned_shape(ctx, lt0, replicas, steps, *schedule, s, step_begin == 0, sh);
+        if (rc) return rc;
+    } else {
+        sh = choose_shape(ctx, replicas, launch, true,
+                          !jt.steps && want_direct(lt0, *schedule, steps));
+    }
     J = make_job(ctx, lt0, replicas, (uint32_t)replica_base, seed, steps, *schedule, sh);
     attach_step_tables(J, jt);
     J.s0 = step_begin;
     J.s1 = step_end;
-    // from here on the state changes: it is resumable again only on success
-    ctx->st_step = -1;
+    if (const char *why = job_range_error(J)) return fail(ctx, DA_EINVAL, why);
     if (step_begin == 0) {
         rc = init_state(ctx, J, schedule->init, s);
         if (rc) return rc;
@@ -1013,6 +1037,17 @@ int da_state_load(da_ctx *ctx, const void *buf, size_t bytes) {
         return fail(ctx, DA_EINVAL, "corrupt snapshot header");
     const int64_t need = da_state_bytes(hdr->N, hdr->replicas);
     if ((int64_t)bytes < need) return fail(ctx, DA_EINVAL, "buffer shorter than the snapshot");
+    {
+        // the step kernel keeps E_offset in [0, 2^30]; a snapshot outside is corrupt
+        const size_t R = (size_t)hdr->replicas, N = (size_t)hdr->N;
+        const uint8_t *eo = static_cast<const uint8_t *>(buf) + sizeof(da_state_header) +
+                            6 * R * N + 24 * R;
+        for (size_t r = 0; r < R; ++r) {
+            int32_t v;
+            std::memcpy(&v, eo + 4 * r, 4);
+            if (v < 0 || v > kEoffMax) return fail(ctx, DA_EINVAL, "snapshot offset out of range");
+        }
+    }
     std::string err;
     ctx->st_step = -1;
     if (!ctx->st.ensure(hdr->replicas, ctx->ld, err)) return fail(ctx, DA_ENOMEM, err);
@@ -1056,6 +1091,9 @@ int da_anneal_batch(const da_batch_item *items, int32_t count, void *stream) {
     std::vector<BatchItem> work;
     std::vector<std::shared_ptr<LevelTables>> keep;
     std::vector<std::shared_ptr<StepTables>> keep_steps;
+    // no context claims a resumable state until the whole batch has run
+    for (int32_t a = 0; a < count; ++a)
+        if (items[a].ctx) items[a].ctx->st_step = -1;
     for (int32_t a = 0; a < count; ++a) {
         const da_batch_item &it = items[a];
         da_ctx *ctx = it.ctx;
@@ -1080,11 +1118,9 @@ int da_anneal_batch(const da_batch_item *items, int32_t count, void *stream) {
         jobs[(size_t)a] = make_job(ctx, *lt, it.replicas, (uint32_t)it.replica_base, it.seed,
                                    it.steps, it.schedule, sh);
         attach_step_tables(jobs[(size_t)a], jt);
+        if (const char *why = job_range_error(jobs[(size_t)a])) return fail(ctx, DA_EINVAL, why);
         rc = init_state(ctx, jobs[(size_t)a], it.schedule.init, s);
         if (rc) return rc;
-        ctx->st_step = it.steps;
-        ctx->st_base = it.replica_base;
-        ctx->st_R = it.replicas;
         if (it.steps > 0) append_batch_items(jobs[(size_t)a], a, work);
         record_stats(ctx, sh, 1);
     }
@@ -1109,7 +1145,14 @@ int da_anneal_batch(const da_batch_item *items, int32_t count, void *stream) {
         rc = extract_outputs(items[a].ctx, jobs[(size_t)a], items[a].replicas, &items[a].out_dev, s);
     // descriptor tables are reused by the next batch: finish this one first
     if (!rc) rc = check_hip(c0, hipStreamSynchronize(s), "stream synchronise");
-    return rc;
+    if (rc) return rc;
+    for (int32_t a = 0; a < count; ++a) {
+        da_ctx *ctx = items[a].ctx;
+        ctx->st_step = items[a].steps;
+        ctx->st_base = items[a].replica_base;
+        ctx->st_R = items[a].replicas;
+    }
+    return DA_OK;
 }
 
 int da_pt(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t rounds,
@@ -1173,6 +1216,7 @@ int da_pt(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t r
     J.lvl_of_rep = ctx->pt_lvl;
     J.round_ptr = ctx->pt_round;
     J.K = steps_per_round;
+    if (const char *why = job_range_error(J)) return fail(ctx, DA_EINVAL, why);
     rc = init_state(ctx, J, DA_INIT_RANDOM, s);
     if (!rc) rc = check_hip(ctx, (hipError_t)launch_pt_setup(ctx->pt_slot2rep, ctx->pt_lvl, ctx->pt_swaps, ctx->pt_round, M, chains, s), "PT setup");
     hipEvent_t pe0 = nullptr, pe1 = nullptr;
@@ -1293,6 +1337,11 @@ const char *da_last_error(const da_ctx *ctx) {
     if (ctx) return ctx->err.c_str();
     return t_err.c_str();
 }
+
+#ifndef DAPT_BUILD_ID
+#define DAPT_BUILD_ID "unknown"
+#endif
+const char *da_build_id(void) { return DAPT_BUILD_ID; }
 
 const char *da_strerror(int status) {
     switch (status) {

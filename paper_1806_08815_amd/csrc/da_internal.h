@@ -101,6 +101,32 @@ struct JobDesc {
     const uint32_t *ell;         // [N][ell_D] column | value << 16, or null
 };
 
+constexpr int64_t kMaxPerStepSteps = int64_t(1) << 24;
+
+// Host guard of every step-kernel launch.  Anneal mode: the step range
+// [s0, s1) lies inside the S-step schedule, so the level index
+// floor(s L / S) of every step it runs stays below L; the offset increment is
+// in [0, 2^30] (the kernel saturates the offset as min(E_off, 2^30 - inc) +
+// inc, which equals min(E_off + inc, 2^30) only there); a per-step schedule
+// has at most 2^24 steps.  Parallel-tempering mode (round counter on the
+// device): a level per replica and a non-negative round length.  Returns
+// nullptr when the job may be launched, else what is wrong.
+inline const char *job_range_error(const JobDesc &J) {
+    if (J.R < 1 || J.N < 1 || J.N > kMaxN || J.ld < J.N || (J.ld & 63) != 0)
+        return "job has no replicas or an inconsistent size";
+    if (J.NW < 1 || J.NH < 0 || J.RPW < 1 || J.NW * J.RPW + J.NH * J.RPW > 16)
+        return "launch shape exceeds one workgroup";
+    if (J.eoff_inc < 0 || J.eoff_inc > kEoffMax) return "offset increment outside [0, 2^30]";
+    if (J.L < 1 || !J.hdr) return "job has no temperature levels";
+    if (J.round_ptr) {
+        if (!J.lvl_of_rep || J.K < 0) return "parallel-tempering job without levels or round";
+        return nullptr;
+    }
+    if (J.s0 < 0 || J.s0 > J.s1 || J.s1 > J.S)
+        return "step range [s0, s1) leaves the schedule's [0, S)";
+    if (J.stepT && J.S > kMaxPerStepSteps) return "per-step schedule longer than 2^24 steps";
+    return nullptr;
+}
 struct TraceDesc {
     int32_t *k;
     int64_t *E;

@@ -163,9 +163,11 @@ __device__ __forceinline__ void update_i16(const typename VecOf<WT, F>::type &ra
     }
 }
 
-// Level in force at step s of an S-step, L-level schedule: floor(s L / S).
+// Level in force at step s of an S-step, L-level schedule: floor(s L / S),
+// clamped to the last level (the host never launches steps s >= S; the clamp
+// keeps a level-table read in range whatever it is given).
 __device__ __forceinline__ int level_of(int64_t s, int32_t L, int64_t S) {
-    return S > 0 ? (int)((s * (int64_t)L) / S) : 0;
+    return S > 0 ? min((int)((s * (int64_t)L) / S), L - 1) : 0;
 }
 
 // First step whose level exceeds `lvl`.
@@ -272,6 +274,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     constexpr bool stage = STAGE;
     const bool sync = HELP || NW > 1;       // a workgroup barrier every step
     const int nblk = (J.N + 7) >> 3;        // Philox blocks per replica-step
+    const int eoff_cap = kEoffMax - J.eoff_inc;   // the host keeps inc in [0, 2^30]
 
     int64_t s0 = J.s0, s1 = J.s1;
     if (J.round_ptr) {
@@ -836,7 +839,8 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             }
             eoff = 0;
         } else {
-            eoff = min(eoff + J.eoff_inc, kEoffMax);
+            // min(E_off + inc, 2^30) without leaving int32 (E_off, inc in [0, 2^30])
+            eoff = min(eoff, eoff_cap) + J.eoff_inc;
             k = -1;
         }
         if (HELP) {
@@ -1319,6 +1323,7 @@ int launch_run_w(const JobDesc &J, int F, bool help, const TraceDesc *trace, int
 
 int launch_run(const JobDesc &J, int F, bool help, const TraceDesc *trace, int blocks,
                int threads, size_t lds_bytes, void *stream) {
+    if (job_range_error(J) != nullptr) return (int)hipErrorInvalidValue;
     if (J.ell && !J.lvl_of_rep)
         return launch_run_w<int16_t>(J, F, help, trace, blocks, threads, lds_bytes, stream);
     switch (J.dtype) {

@@ -77,30 +77,32 @@ int run_probe(int32_t n_rows, int32_t row_elems, int32_t chains, int32_t waves, 
         return DA_ENOMEM;
     }
     int rc = DA_OK;
-    hipEvent_t a, b;
-    (void)hipEventCreate(&a);
-    (void)hipEventCreate(&b);
-    if (hipMemcpy(dM, host.data(), host.size() * sizeof(WT), hipMemcpyHostToDevice) != hipSuccess)
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) rc = DA_EDEVICE;
+    if (!rc &&
+        hipMemcpy(dM, host.data(), host.size() * sizeof(WT), hipMemcpyHostToDevice) != hipSuccess)
         rc = DA_EDEVICE;
+    float ms = 0.f;
     if (!rc) {
         // warm caches with a short run, then time
         hipLaunchKernelGGL(k_row_chase<WT>, dim3(chains), dim3(64 * waves), 0, 0, dM, ld, n_rows,
                            (int64_t)(steps / 10 + 1), sink);
-        (void)hipEventRecord(a, 0);
-        hipLaunchKernelGGL(k_row_chase<WT>, dim3(chains), dim3(64 * waves), 0, 0, dM, ld, n_rows,
-                           steps, sink);
-        (void)hipEventRecord(b, 0);
-        if (hipEventSynchronize(b) != hipSuccess) rc = DA_EDEVICE;
+        if (hipGetLastError() != hipSuccess || hipEventRecord(a, 0) != hipSuccess) rc = DA_EDEVICE;
     }
     if (!rc) {
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, a, b);
+        hipLaunchKernelGGL(k_row_chase<WT>, dim3(chains), dim3(64 * waves), 0, 0, dM, ld, n_rows,
+                           steps, sink);
+        if (hipGetLastError() != hipSuccess || hipEventRecord(b, 0) != hipSuccess ||
+            hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess)
+            rc = DA_EDEVICE;
+    }
+    if (!rc) {
         const double t = ms * 1e-3;
         *ns_per_step = t / (double)steps * 1e9;
         *gbytes_per_s = (double)row_elems * sizeof(WT) * chains * (double)steps / t / 1e9;
     }
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
     (void)hipFree(dM);
     (void)hipFree(sink);
     return rc;
@@ -154,22 +156,21 @@ extern "C" int da_probe_fields_mfma(int32_t N, int32_t R, int32_t iters, double 
         J.ld = ld;
         J.dtype = 1;
         J.wscale = 1;
-        (void)hipEventCreate(&a);
-        (void)hipEventCreate(&b);
-        if (dapt::launch_fields(J, dX, R, dH, nullptr) != 0) rc = DA_EDEVICE;
-        (void)hipEventRecord(a, 0);
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) rc = DA_EDEVICE;
+        if (!rc && dapt::launch_fields(J, dX, R, dH, nullptr) != 0) rc = DA_EDEVICE;
+        if (!rc && hipEventRecord(a, 0) != hipSuccess) rc = DA_EDEVICE;
         for (int32_t q = 0; q < iters && !rc; ++q)
             if (dapt::launch_fields(J, dX, R, dH, nullptr) != 0) rc = DA_EDEVICE;
-        (void)hipEventRecord(b, 0);
-        if (!rc && hipEventSynchronize(b) != hipSuccess) rc = DA_EDEVICE;
+        float ms = 0.f;
+        if (!rc && (hipEventRecord(b, 0) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                    hipEventElapsedTime(&ms, a, b) != hipSuccess))
+            rc = DA_EDEVICE;
         if (!rc) {
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, a, b);
             *ms_per_call = ms / iters;
             *tera_ops = 2.0 * ld * (double)ld * R / (*ms_per_call * 1e-3) / 1e12;
         }
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(b);
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
     }
     (void)hipFree(dW);
     (void)hipFree(dX);

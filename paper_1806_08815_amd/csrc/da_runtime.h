@@ -41,7 +41,6 @@ struct StepTables {
     size_t bytes = 0;
     ~StepTables();
 };
-constexpr int64_t kMaxPerStepSteps = int64_t(1) << 24;
 std::shared_ptr<StepTables> get_step_tables(const da_schedule &s, int64_t S, std::string &err);
 const double *device_neg_log_u(std::string &err);
 // Band header and brackets of one level from its threshold table.
@@ -169,6 +168,7 @@ struct da_ctx {
     int32_t dtype = 0;     // bytes per stored coupling
     int32_t wscale = 1;
     int device = 0;
+    int cus = 256;               // compute units of the device
     void *d_W = nullptr;
     int32_t *d_b = nullptr;
     uint32_t *d_ell = nullptr;   // sparse row lists [N][ell_D], or null
@@ -209,9 +209,11 @@ int validate_schedule(const da_schedule *s, std::string &err);
 LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch,
                          bool anneal_mode, bool direct = false);
 // Fastest measured shape for this instance size, coupling type and replica
-// count (timed once on scratch state, then cached).
-LaunchShape tuned_shape(da_ctx *ctx, const LevelTables &lt, int32_t R, int64_t steps,
-                        const da_schedule &sched, hipStream_t s);
+// count, into `out`: timed once (when may_time) on the context's replica state,
+// which must hold R replicas and is left overwritten, then cached.  Returns
+// DA_OK, or the error of the first HIP call that failed (naming the candidate).
+int tuned_shape(da_ctx *ctx, const LevelTables &lt, int32_t R, int64_t steps,
+                const da_schedule &sched, hipStream_t s, bool may_time, LaunchShape &out);
 JobDesc make_job(const da_ctx *ctx, const LevelTables &lt, int32_t R, uint32_t rid_base,
                  uint64_t seed, int64_t steps, const da_schedule &s, const LaunchShape &sh);
 int init_state(da_ctx *ctx, const JobDesc &J, int init, hipStream_t stream);

@@ -227,7 +227,9 @@ void da_server::retire(std::unique_ptr<Job> &jp) {
 // epoch in flight), finish that epoch, retire, then launch the next epoch
 // without waiting for it.
 void da_server::run() {
-    (void)hipSetDevice(device);
+    // every launch and copy of this thread goes to the server's device; if it
+    // cannot be selected, every job fails with that error instead of running
+    const hipError_t dev_err = hipSetDevice(device);
     std::vector<Job *> in_epoch;
     std::vector<JobDesc> jobs;
     bool inflight = false;
@@ -250,7 +252,13 @@ void da_server::run() {
             }
         }
         for (Job *j : admitted) {
-            j->status = start_job(*j);
+            if (dev_err != hipSuccess) {
+                j->status = DA_EDEVICE;
+                j->err = std::string("server device selection failed: ") +
+                         hipGetErrorString(dev_err);
+            } else {
+                j->status = start_job(*j);
+            }
             j->stats.device_bytes = j->footprint;
         }
         if (inflight) {
@@ -365,7 +373,10 @@ int da_server_create(size_t hbm_budget, const da_server_opts *opts, da_server **
     if (opts && opts->max_resident > 0)
         srv->max_resident = std::min<int32_t>(opts->max_resident, BatchRunner::kCapJobs);
     srv->t0 = std::chrono::steady_clock::now();
-    (void)hipGetDevice(&srv->device);
+    if (hipGetDevice(&srv->device) != hipSuccess) {
+        delete srv;
+        return fail(nullptr, DA_EDEVICE, "no current HIP device");
+    }
     if (hipStreamCreateWithFlags(&srv->stream, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&srv->upload, hipStreamNonBlocking) != hipSuccess) {
         if (srv->stream) (void)hipStreamDestroy(srv->stream);

@@ -5,6 +5,7 @@
 // flip, direct table) agree with the definition d <= thr[u] of the Metropolis
 // test as a threshold on the 16-bit draw; and the autotuner's timing window
 // stays inside its schedule.  Exit status 0 when every check holds.
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -121,6 +122,72 @@ int main() {
         tune_window(S, s0, s1);
         CHECK(s0 >= 0 && s1 <= S && s1 - s0 == (S < 384 ? S : 384), "tune window S=%lld",
               (long long)S);
+    }
+    // the host guard of every step-kernel launch: a step range inside the
+    // schedule passes (the autotuner's window included), anything reaching
+    // step S or beyond -- where the level index would leave the tables -- and
+    // offset increments that could overflow the saturating update do not
+    {
+        LevelHdr hdr0{};
+        JobDesc J{};
+        J.N = 1000;
+        J.ld = 1024;
+        J.R = 8;
+        J.NW = 2;
+        J.NH = 2;
+        J.RPW = 1;
+        J.L = 128;
+        J.hdr = &hdr0;
+        J.eoff_inc = 1;
+        for (int64_t S : {1, 2, 63, 64, 383, 384, 575, 576, 100000}) {
+            J.S = S;
+            J.s0 = 0;
+            J.s1 = S;
+            CHECK(job_range_error(J) == nullptr, "guard rejects the whole schedule S=%lld",
+                  (long long)S);
+            tune_window(S, J.s0, J.s1);
+            CHECK(job_range_error(J) == nullptr, "guard rejects the tuner window S=%lld",
+                  (long long)S);
+            J.s0 = S / 3;              // the old window: starts at S/3 whatever S
+            J.s1 = J.s0 + 384;
+            CHECK((job_range_error(J) == nullptr) == (J.s1 <= S),
+                  "guard and a window past the end disagree, S=%lld", (long long)S);
+            J.s0 = 0;
+            J.s1 = S + 1;
+            CHECK(job_range_error(J) != nullptr, "guard lets s1 = S + 1 through");
+            J.s0 = -1;
+            J.s1 = S;
+            CHECK(job_range_error(J) != nullptr, "guard lets s0 < 0 through");
+            J.s0 = S;
+            J.s1 = S - 1;
+            CHECK(job_range_error(J) != nullptr, "guard lets s0 > s1 through");
+        }
+        J.S = 1000;
+        J.s0 = 0;
+        J.s1 = 1000;
+        for (int32_t inc : {0, 1, 65536, kEoffMax}) {
+            J.eoff_inc = inc;
+            CHECK(job_range_error(J) == nullptr, "guard rejects increment %d", inc);
+        }
+        J.eoff_inc = kEoffMax + 1;
+        CHECK(job_range_error(J) != nullptr, "guard lets an increment above 2^30 through");
+        J.eoff_inc = -1;
+        CHECK(job_range_error(J) != nullptr, "guard lets a negative increment through");
+        J.eoff_inc = 1;
+        J.NW = 15;                    // 15 + 2 waves do not fit one workgroup
+        CHECK(job_range_error(J) != nullptr, "guard lets 17 waves through");
+        J.NW = 2;
+        J.L = 0;
+        CHECK(job_range_error(J) != nullptr, "guard lets a job without levels through");
+        // the saturating offset update equals min(E_off + inc, 2^30) over [0, 2^30]
+        for (int64_t e : {int64_t(0), int64_t(1), int64_t(kEoffMax) - 1, int64_t(kEoffMax)})
+            for (int64_t inc : {int64_t(0), int64_t(1), int64_t(1) << 29, int64_t(kEoffMax)}) {
+                const int32_t cap = kEoffMax - (int32_t)inc;
+                const int64_t got = (int64_t)std::min<int32_t>((int32_t)e, cap) + inc;
+                const int64_t want = std::min<int64_t>(e + inc, kEoffMax);
+                CHECK(got == want, "offset update e=%lld inc=%lld", (long long)e,
+                      (long long)inc);
+            }
     }
     std::printf("levels %ld decisions %ld failures %ld\n", levels, decisions, g_bad);
     return g_bad != 0;

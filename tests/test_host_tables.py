@@ -6,7 +6,10 @@ and reject-all entry fit the LDS staging area where the kernel looks for them;
 the band-test form, the one-bracket-read form and the direct-table form of the
 acceptance test each equal d <= thr[u] (the Metropolis test of Algorithm 2 on
 the 16-bit draw) for costs across the band, beyond it and at the ends of the int32
-range; and the autotuner's timing window stays inside its schedule.  Planting
+range; the autotuner's timing window stays inside its schedule; and the host
+guard of every step-kernel launch (job_range_error) passes every step range
+inside a schedule and rejects ranges reaching step S or beyond, negative or
+reversed ranges, offset increments above 2^30 and oversized shapes.  Planting
 either of two past mistakes (the last bucket's cut clamped to tmax, a window
 starting at S/3 for every S) makes it fail.  Host code only: runs on the CPU.
 """

@@ -84,3 +84,115 @@ def test_pt_rejects_bad_ladders(orc):
         orc.pt(Q, [3.0, 2.0], chains=1, rounds=1, steps_per_round=1)
     with pytest.raises(ValueError):
         orc.pt(Q, [0.0, 2.0], chains=1, rounds=1, steps_per_round=1)
+
+
+# --- the exchange sweep over a ladder of M >= 3 rungs -------------------------
+#
+# With K = 0 the replicas' energies are frozen at their random starts, and the
+# rounds form a Markov chain over the M! assignments of replicas to slots.
+# Every pair move of the sweep is a Metropolis swap at (1/T_p - 1/T_{p+1}), so
+# the whole sweep leaves the Boltzmann weights
+#     P(pi) ~ exp(-sum_p E_{pi(p)} / T_p)     (pi(p): replica in slot p)
+# invariant (Sec. II.D; the exchange move of Algorithm 3).  The long-run
+# frequencies of the M! assignments must therefore match P, which a sweep that
+# decided pair p on the slots held before the earlier swaps of the same sweep
+# does not do (checked below with such a sweep written here).
+
+def _perm_counts(slot_trace, M, burn, thin):
+    from itertools import permutations
+    index = {pm: q for q, pm in enumerate(permutations(range(M)))}
+    counts = np.zeros(len(index))
+    for slots in slot_trace[burn::thin]:
+        # slots[replica] = slot -> replica in each slot
+        ris = [0] * M
+        for r, p in enumerate(slots):
+            ris[p] = r
+        counts[index[tuple(ris)]] += 1
+    return counts, list(index)
+
+
+def _boltzmann(E, temps, perms):
+    logw = np.array([-sum(E[pm[p]] / temps[p] for p in range(len(temps))) for pm in perms])
+    w = np.exp(logw - logw.max())
+    return w / w.sum()
+
+
+def _ladder_for(E, M):
+    """Temperatures that make every adjacent exchange a coin flip of moderate
+    bias for these frozen energies (so the chain mixes in a few rounds)."""
+    spread = max(1.0, float(np.std(E)))
+    step = (1.2 if M == 3 else 0.9) / ((M - 1) * spread)
+    betas = 0.02 + np.arange(M)[::-1] * step
+    return 1.0 / betas
+
+
+def _chi2_pvalue(counts, probs):
+    from scipy import stats
+    exp = counts.sum() * probs
+    chi2 = float(((counts - exp) ** 2 / exp).sum())
+    return stats.chi2.sf(chi2, len(counts) - 1)
+
+
+@pytest.mark.parametrize("M,N,inst", [(3, 20, 11), (4, 16, 12)])
+def test_exchange_sweep_boltzmann_multirung(orc, M, N, inst):
+    Q, _ = instances.ising_to_qubo(instances.sk_bimodal(N, inst))
+    start = orc.pt(Q, [1.0 + p for p in range(M)], chains=1, rounds=0, steps_per_round=0,
+                   seed=5)
+    E = start["final_E"].astype(np.float64)
+    assert len(set(E.tolist())) == M, "frozen energies must differ"
+    temps = _ladder_for(E, M)
+    rounds = 40_000 if M == 3 else 120_000
+    out = orc.pt(Q, temps, chains=1, rounds=rounds, steps_per_round=0, seed=5, slot_trace=True)
+    counts, perms = _perm_counts(out["slot_trace"][0], M, burn=100, thin=10)
+    probs = _boltzmann(E, temps, perms)
+    assert probs.min() > 0.005, probs   # every assignment is visited often
+    p = _chi2_pvalue(counts, probs)
+    assert p > 1e-4, (p, counts, counts.sum() * probs)
+    # the frozen energies are the random starts, untouched by the sweeps
+    np.testing.assert_array_equal(out["final_E"], start["final_E"])
+
+
+def test_stale_slot_sweep_fails_the_boltzmann_check(orc):
+    # The same check applied to a sweep that decides pair p on the slots held
+    # at the start of the sweep (a stale read) rejects it: the pin has power.
+    M, N = 3, 20
+    Q, _ = instances.ising_to_qubo(instances.sk_bimodal(N, 11))
+    E = orc.pt(Q, [1.0, 2.0, 3.0], chains=1, rounds=0, steps_per_round=0,
+               seed=5)["final_E"].astype(np.float64)
+    temps = _ladder_for(E, M)
+    lnU = np.log((np.arange(65536) + 0.5) / 65536.0)
+    ris = list(range(M))
+    trace = []
+    for t in range(40_000):
+        held = list(ris)
+        for p in range(M - 1):
+            a, b = held[p], held[p + 1]
+            delta = (1.0 / temps[p] - 1.0 / temps[p + 1]) * (E[a] - E[b])
+            if lnU[orc.exchange_draw(5, 0, t, p)] < delta:
+                ris[p], ris[p + 1] = ris[p + 1], ris[p]
+        slots = [0] * M
+        for p, r in enumerate(ris):
+            slots[r] = p
+        trace.append(slots)
+    counts, perms = _perm_counts(np.array(trace), M, burn=100, thin=10)
+    assert _chi2_pvalue(counts, _boltzmann(E, temps, perms)) < 1e-6
+
+
+def test_pair_swaps_add_up(orc):
+    Q, _ = instances.ising_to_qubo(instances.sk_bimodal(32, 8))
+    temps = np.geomspace(2.0, 20.0, 5)
+    out = orc.pt(Q, temps, chains=3, rounds=30, steps_per_round=16, seed=2)
+    assert out["pair_swaps"].shape == (3, 4)
+    np.testing.assert_array_equal(out["pair_swaps"].sum(axis=1), out["n_swaps"])
+
+
+def test_chain_base_selects_chains(orc):
+    # chains are independent: chain c run alone equals chain c of a larger run
+    Q, _ = instances.ising_to_qubo(instances.sk_bimodal(24, 9))
+    temps = np.geomspace(1.5, 12.0, 4)
+    full = orc.pt(Q, temps, chains=3, rounds=6, steps_per_round=20, eoff_inc=1, seed=7)
+    one = orc.pt(Q, temps, chains=1, rounds=6, steps_per_round=20, eoff_inc=1, seed=7,
+                 chain_base=2)
+    for k in ("best_x", "best_E", "final_x", "final_E", "n_accept", "slot"):
+        np.testing.assert_array_equal(one[k], full[k][8:12])
+    np.testing.assert_array_equal(one["n_swaps"], full["n_swaps"][2:])
