@@ -88,6 +88,11 @@ def lib() -> ctypes.CDLL:
         L.orc_pt_ex.restype = ctypes.c_int
         L.orc_pt_sweep.argtypes = [ctypes.c_int, P, P, P, P, u64, u32, u32, P]
         L.orc_pt_sweep.restype = i64
+        L.orc_ladder_update.argtypes = [ctypes.c_int, P, P, i64, P]
+        L.orc_ladder_update.restype = None
+        L.orc_pt_adapt.argtypes = [ctypes.c_int, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   i64, ctypes.c_int, i64, u64, P]
+        L.orc_pt_adapt.restype = ctypes.c_int
         L.orc_rep_new.argtypes = [ctypes.c_int, P, ctypes.c_int, u64, u32]
         L.orc_rep_new.restype = P
         L.orc_rep_step.argtypes = [P, P, u64, u32, u32, i64]
@@ -255,6 +260,30 @@ def pt_sweep(E, temps, replica_in_slot, seed: int, chain: int, round_: int):
     lib().orc_pt_sweep(M, _p(E), _p(t), _p(lnU), _p(ris), ctypes.c_uint64(seed), int(chain),
                        int(round_), _p(ps))
     return ris, ps[:max(M - 1, 0)]
+
+
+def ladder_update(temps, accepted, proposals: int) -> np.ndarray:
+    """One adaptive-ladder update (ends fixed, intervals toward equal acceptance)."""
+    t = np.ascontiguousarray(np.asarray(temps, dtype=np.float64))
+    a = np.ascontiguousarray(np.asarray(accepted, dtype=np.int64))
+    out = np.zeros_like(t)
+    lib().orc_ladder_update(t.shape[0], _p(t), _p(a), int(proposals), _p(out))
+    return out
+
+
+def pt_adapt(Q, temps, *, chains: int, iterations: int, rounds: int, steps_per_round: int,
+             eoff_inc: int = 0, seed: int = 1):
+    """Adapted ladder and the acceptances [iterations][M-1] measured on the way."""
+    Q = _q(Q)
+    t = np.ascontiguousarray(np.asarray(temps, dtype=np.float64)).copy()
+    M = t.shape[0]
+    acc = np.zeros((int(iterations), max(M - 1, 1)))
+    rc = lib().orc_pt_adapt(Q.shape[0], _p(Q), _p(t), M, int(chains), int(iterations),
+                            int(rounds), int(steps_per_round), int(eoff_inc),
+                            ctypes.c_uint64(seed), _p(acc))
+    if rc != 0:
+        raise ValueError("oracle pt_adapt rejected its arguments")
+    return t, acc[:, :max(M - 1, 0)]
 
 
 class Replica:

@@ -483,6 +483,81 @@ int orc_pt(int N, const int32_t *Q, const double *temps, int M, int chains,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Adaptive temperature ladder (Sec. II.D: the PTDA sets its temperatures    */
+/* by the adaptive scheme of Hukushima et al.; the lowest and highest        */
+/* temperatures stay fixed and the ones between are moved toward equal       */
+/* replica-exchange acceptance for every adjacent pair).                     */
+/*                                                                           */
+/* One update, in inverse temperatures beta_p = 1/T_p (decreasing in p):     */
+/* with interval d_p = beta_p - beta_{p+1} and measured acceptance A_p of    */
+/* pair p (accepted / proposals, floored at half a swap so that no interval  */
+/* collapses), the new intervals are proportional to d_p * A_p and fill the  */
+/* fixed span beta_0 - beta_{M-1}:                                           */
+/*   d'_p = (beta_0 - beta_{M-1}) * (w_p / sum_q w_q),  w_p = d_p * A_p,      */
+/*   beta'_0 = beta_0,  beta'_{p+1} = beta'_p - d'_p,  T'_{M-1} = T_{M-1}.    */
+/* A pair that accepts more than the others gets a wider interval (which      */
+/* lowers its acceptance) and one that accepts less a narrower one; equal     */
+/* acceptances are the fixed point.                                          */
+/* ------------------------------------------------------------------------ */
+void orc_ladder_update(int M, const double *temps, const int64_t *accepted, int64_t proposals,
+                       double *out)
+{
+    for (int p = 0; p < M; ++p) out[p] = temps[p];
+    if (M < 3 || proposals < 1) return;
+    double beta_lo_T = 1.0 / temps[0];          /* coldest: largest beta */
+    double beta_hi_T = 1.0 / temps[M - 1];
+    double floor_acc = 0.5 / (double)proposals;
+    double total = 0.0;
+    double *w = malloc(sizeof(double) * (size_t)(M - 1));
+    if (!w) return;
+    for (int p = 0; p + 1 < M; ++p) {
+        double acc = (double)accepted[p] / (double)proposals;
+        if (acc < floor_acc) acc = floor_acc;
+        w[p] = (1.0 / temps[p] - 1.0 / temps[p + 1]) * acc;
+        total += w[p];
+    }
+    double beta = beta_lo_T;
+    for (int p = 0; p + 2 < M; ++p) {
+        beta = beta - (beta_lo_T - beta_hi_T) * (w[p] / total);
+        out[p + 1] = 1.0 / beta;
+    }
+    free(w);
+}
+
+/* Ladder adaptation by repeated PT runs: iteration i runs `chains` chains of
+ * `rounds` rounds (K DA steps each, random starts, seed + i) on the current
+ * ladder, measures every pair's acceptance over all chains and rounds, and
+ * updates the ladder.  temps is updated in place; acceptance [iterations][M-1]
+ * (nullable) receives the measured acceptances of each iteration. */
+int orc_pt_adapt(int N, const int32_t *Q, double *temps, int M, int chains, int iterations,
+                 int64_t rounds, int K, int64_t eoff_inc, uint64_t seed, double *acceptance)
+{
+    if (M < 2 || chains < 1 || iterations < 0 || rounds < 1) return -1;
+    int64_t *ps = calloc((size_t)chains * (size_t)(M - 1), sizeof(int64_t));
+    int64_t *acc = malloc(sizeof(int64_t) * (size_t)(M - 1));
+    double *next = malloc(sizeof(double) * (size_t)M);
+    if (!ps || !acc || !next) { free(ps); free(acc); free(next); return -1; }
+    int rc = 0;
+    for (int it = 0; it < iterations && rc == 0; ++it) {
+        memset(ps, 0, sizeof(int64_t) * (size_t)chains * (size_t)(M - 1));
+        rc = orc_pt_ex(N, Q, temps, M, 0, chains, rounds, K, eoff_inc, seed + (uint64_t)it,
+                       NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, ps);
+        if (rc) break;
+        const int64_t proposals = (int64_t)chains * rounds;
+        for (int p = 0; p + 1 < M; ++p) {
+            acc[p] = 0;
+            for (int c = 0; c < chains; ++c) acc[p] += ps[(size_t)c * (M - 1) + p];
+            if (acceptance)
+                acceptance[(size_t)it * (M - 1) + p] = (double)acc[p] / (double)proposals;
+        }
+        orc_ladder_update(M, temps, acc, proposals, next);
+        for (int p = 0; p < M; ++p) temps[p] = next[p];
+    }
+    free(ps); free(acc); free(next);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Step-level access for the invariant tests: build a replica state, step it */
 /* one Monte Carlo step at a time, read it back.                             */
 /* ------------------------------------------------------------------------ */

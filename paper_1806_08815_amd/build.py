@@ -52,7 +52,8 @@ def build_library(verbose: bool = False) -> str:
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
               "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
     build_id = source_hash()
-    for src in SOURCES:
+
+    def compile_one(src):
         obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
         cmd = [hipcc(), *common, "-c", os.path.join(CSRC, src), "-o", obj]
         if src == "da_api.cpp":
@@ -66,7 +67,12 @@ def build_library(verbose: bool = False) -> str:
             raise RuntimeError(f"hipcc failed on {src}:\n{err}")
         if verbose and err.strip():
             print(err, file=sys.stderr)
-        objs.append(obj)
+        return obj
+
+    # the sources compile independently: all at once
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -594,14 +594,19 @@ int tuned_shape(da_ctx *ctx, const LevelTables &lt, int32_t R, int64_t steps,
     if (!rc) rc = check_hip(ctx, hipEventCreate(&b), "autotuner: event create");
     da_launch best{0, 0, 0, 0};
     float best_ms = 1e30f;
+    // W staged in LDS is a candidate whenever it fits there
+    const bool w_fits = ctx->ell_D == 0 &&
+                        (int64_t)ctx->N * ctx->ld * ctx->dtype <= (int64_t)device_lds_limit();
     for (int F : {4, 8}) {
         for (int rpw : {1, 2, 4}) {
-            for (int rng : {1, -1}) {
+            for (int rng : {1, -1})
+            for (int wl : {-1, 1}) {
                 if (rc) break;
-                const da_launch cand{F, rpw, 0, rng};
+                if (wl > 0 && !w_fits) continue;
+                const da_launch cand{F, rpw, wl, rng};
                 const LaunchShape sh = choose_shape(ctx, R, &cand, true, direct);
-                if (sh.RPW != rpw || sh.F != F || sh.threads > 1024 ||
-                    sh.lds > (size_t)device_lds_limit())
+                if (sh.RPW != rpw || sh.F != F || sh.w_lds != (wl > 0 ? 1 : 0) ||
+                    sh.threads > 1024 || sh.lds > (size_t)device_lds_limit())
                     continue;
                 JobDesc J = make_job(ctx, lt, R, 0u, 1u, steps, sched, sh);
                 tune_window(steps, J.s0, J.s1);
@@ -614,7 +619,7 @@ int tuned_shape(da_ctx *ctx, const LevelTables &lt, int32_t R, int64_t steps,
                 char what[160];
                 std::snprintf(what, sizeof what,
                               "autotuner candidate (flips/lane %d, replicas/workgroup %d, "
-                              "rng waves %d)", F, rpw, rng);
+                              "rng waves %d, W in LDS %d)", F, rpw, rng, wl);
                 rc = check_hip(ctx, (hipError_t)launch_state_zero(J, s), what);
                 if (!rc) rc = check_hip(ctx, hipEventRecord(a, s), what);
                 if (!rc)

@@ -129,6 +129,50 @@ def test_server_results_equal_alone(api):
     # somebody had to wait for memory
     assert max(g["stats"]["t_admit"] - g["stats"]["t_submit"] for g in got) > 0
     srv.close()
+    # and the oracle: one sampled replica of every served job, replayed alone
+    for a, (kind, N, R, S, init, hint, L) in enumerate(specs):
+        _oracle_replica(kind, N, 40 + a, R - 1 - a % R, S, init, L, 7 + a, got[a])
+
+
+def _oracle_replica(kind, N, inst, r, S, init, L, seed, got):
+    Q, t = _job(kind, N, inst)
+    ref = oracle.anneal(Q, T_hi=t["T_hi"], T_lo=t["T_lo"], n_levels=L, eoff_inc=t["eoff_inc"],
+                        init=0 if init == "zeros" else 1, replica_base=r, replicas=1, steps=S,
+                        seed=seed)
+    for k in KEYS:
+        assert np.array_equal(np.asarray(got[k])[r], ref[k][0]), (kind, N, r, k)
+
+
+def test_server_large_jobs_vs_oracle(api):
+    """The largest served sizes: an N = 8192 +-1 job and int32-stored Gaussian
+    jobs (N = 4096 and 2048) beside small ones, under a budget that holds the
+    big jobs one at a time, so they queue; every result equals the job alone
+    and, for one sampled replica per job, the oracle."""
+    specs = [("sk", 8192, 3, 400, "zeros", 0, 8), ("gauss", 4096, 4, 500, "random", 4, 16),
+             ("gauss", 2048, 6, 900, "zeros", 4, 32), ("sk", 256, 24, 1500, "zeros", 0, 64),
+             ("gauss", 77, 11, 2000, "random", 4, 16)]
+    jobs, want, foot = [], [], []
+    for a, (kind, N, R, S, init, hint, L) in enumerate(specs):
+        Q, t = _job(kind, N, 90 + a)
+        sch = api.schedule(t["T_hi"], t["T_lo"], "geometric", L, t["eoff_inc"], init)
+        ctx = api.da_create(Q, hint)
+        want.append(api.da_anneal(ctx, sch, R, S, 50 + a))
+        foot.append(api.da_job_footprint(N, ctx.info()["dtype"], R, L))
+        ctx.close()
+        jobs.append((Q, sch, R, S, 50 + a, hint))
+    # room for either big job plus all the small ones, never both big jobs
+    budget = max(foot[:2]) + sum(foot[2:]) + (1 << 20)
+    assert budget < foot[0] + foot[1]
+    srv = api.da_server_create(budget, epoch_steps=333)
+    tickets = [api.da_submit(srv, *j) for j in jobs]
+    got = [api.da_wait(srv, t) for t in tickets]
+    srv.close()
+    for a, (kind, N, R, S, init, hint, L) in enumerate(specs):
+        for k in KEYS:
+            assert np.array_equal(got[a][k], want[a][k]), (specs[a], k)
+    assert got[1]["stats"]["t_admit"] >= got[0]["stats"]["t_done"] - 1e-6
+    for a, (kind, N, R, S, init, hint, L) in enumerate(specs):
+        _oracle_replica(kind, N, 90 + a, R - 1, S, init, L, 50 + a, got[a])
 
 
 def test_server_tickets_and_admission(api):

@@ -327,3 +327,53 @@ def test_single_trial_resume_and_serve(api):
     got = api.da_wait(srv, api.da_submit(srv, Q, sch, 5, 3001, 2))
     srv.close()
     _same(got, whole)
+
+
+@pytest.mark.parametrize("rng", [1, -1])
+@pytest.mark.parametrize("N,F,rpw", [(128, 4, 1), (200, 4, 2), (200, 8, 1), (256, 4, 1),
+                                     (256, 8, 2)])
+def test_w_in_lds_trace_parity(api, N, F, rpw, rng):
+    """16-bit couplings staged in LDS for N up to 256 (128 KiB of W at N = 256):
+    every accepted step reads row k from LDS instead of L2."""
+    Q = _q("random", N, 21)
+    T_hi, T_lo, inc = 4000.0, 10.0, 50
+    R, S, L = 5, 700, 16
+    ctx = api.da_create(Q, 2)
+    assert ctx.info()["dtype"] == 2
+    sch = api.schedule(T_hi, T_lo, "geometric", L, eoff_inc=inc)
+    gpu = api.da_anneal_ex(ctx, sch, 2, R, S, 17, api.launch(F, rpw, 1, rng), trace=True)
+    assert api.da_last_kernel_stats(ctx)["w_in_lds"] == 1
+    ref = oracle.anneal(Q, T_hi=T_hi, T_lo=T_lo, n_levels=L, eoff_inc=inc, replica_base=2,
+                        replicas=R, steps=S, seed=17, trace=True)
+    _same(gpu, ref, ("trace_k", "trace_E", "trace_eoff") + KEYS)
+
+
+@pytest.mark.parametrize("inc", [2**30, 2**31 - 1])
+def test_offset_increment_extremes(api, inc):
+    """Offset increments at and above the 2^30 ceiling (R7): the offset
+    saturates at 2^30 after one rejected step, and the step after accepts every
+    flip; the kernel's update must not leave int32 on the way."""
+    Q = _q("random", 90, 22)
+    ctx = api.da_create(Q)
+    sch = api.schedule(30.0, 2.0, "geometric", 8, eoff_inc=inc)
+    for rng in (1, -1):
+        gpu = api.da_anneal_ex(ctx, sch, 0, 4, 3000, 5, api.launch(4, 1, 0, rng), trace=True)
+        ref = oracle.anneal(Q, T_hi=30.0, T_lo=2.0, n_levels=8, eoff_inc=inc, replicas=4,
+                            steps=3000, seed=5, trace=True)
+        _same(gpu, ref, ("trace_k", "trace_E", "trace_eoff") + KEYS)
+        assert (ref["trace_eoff"] == 2**30).any()
+
+
+def test_snapshot_offset_out_of_range_rejected(api):
+    Q = _q("sk", 64, 3)
+    ctx = api.da_create(Q)
+    sch = api.schedule(3.0, 0.05, eoff_inc=1)
+    api.da_anneal_steps(ctx, sch, 0, 2, 1000, 0, 500, 1)
+    snap = api.da_state_save(ctx, 2)
+    bad = snap.copy()
+    tail = 32 + 2 * 6 * 64 + 2 * 24          # header, x/best x/h, E/best E/accepted
+    bad[tail:tail + 4] = np.frombuffer(np.int32(2**30 + 1).tobytes(), np.uint8)
+    with pytest.raises(api.DaError) as e:
+        api.da_state_load(ctx, bad)
+    assert e.value.code == api.DA_EINVAL
+    api.da_state_load(ctx, snap)

@@ -169,3 +169,26 @@ def test_random_start_large_mfma_fields(api):
                             replica_base=r, replicas=1, steps=40, seed=19)
         for k in KEYS:
             assert np.array_equal(gpu[k][r], ref[k][0]), (r, k)
+
+
+@pytest.mark.timeout(600)
+def test_pt_full_size_sampled_chain(api):
+    """The PT workload at full chain count: 64 chains x 32 temperatures of the
+    N = 1024 +-1 instance, K = 1024 steps per round, 100 rounds on the device;
+    one sampled chain (its 32 replicas, slots and swaps) replayed by the oracle."""
+    p = workloads.PT_WORKLOAD
+    Q, _ = workloads.make_instance(p["kind"], p["N"], p["instance_seed"])
+    temps = workloads.pt_temperatures(p["M"], p["T_lo"], p["T_hi"], p["temp_scale"])
+    M, C, rounds = p["M"], p["chains"], 100
+    ctx = api.da_create(Q)
+    gpu = api.da_pt(ctx, temps, C, rounds, p["steps_per_round"], p["eoff_inc"], p["seed"])
+    c = 37
+    ref = oracle.pt(Q, temps, chains=1, rounds=rounds, steps_per_round=p["steps_per_round"],
+                    eoff_inc=p["eoff_inc"], seed=p["seed"], chain_base=c)
+    rows = slice(c * M, (c + 1) * M)
+    for k in KEYS + ("slot",):
+        assert np.array_equal(gpu[k][rows], ref[k]), k
+    assert gpu["n_swaps"][c] == ref["n_swaps"][0] > 0
+    # every chain's slots are a permutation of the ladder
+    for q in range(C):
+        assert sorted(gpu["slot"][q * M:(q + 1) * M]) == list(range(M))
