@@ -290,7 +290,8 @@ int da_state_load(da_ctx *ctx, const void *buf, size_t bytes);
 
 /* Outputs of parallel tempering, indexed by replica id c*M + m (chain c,
  * replica m); any field may be NULL.  slot: temperature index of each replica
- * at the end; n_swaps [chains]: accepted exchanges per chain. */
+ * at the end; n_swaps [chains]: accepted exchanges per chain; pair_swaps
+ * [chains][M-1]: accepted exchanges of each adjacent pair (p, p+1). */
 typedef struct da_pt_result {
     uint8_t *best_x;
     int64_t *best_E;
@@ -299,6 +300,7 @@ typedef struct da_pt_result {
     int64_t *n_accept;
     int32_t *slot;
     int64_t *n_swaps;
+    int64_t *pair_swaps;
 } da_pt_result;
 
 /* Parallel tempering with DA steps (Sec. II.D, exchange move of Algorithm 3),
@@ -314,6 +316,32 @@ typedef struct da_pt_result {
  * chains < 1, rounds * steps_per_round >= 2^31), DA_ENOMEM, DA_EDEVICE. */
 int da_pt(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t rounds,
           int32_t steps_per_round, int32_t eoff_inc, uint64_t seed, da_pt_result *out);
+
+/* Adaptive temperature ladder (Sec. II.D: the PTDA sets its temperatures by
+ * the adaptive scheme of Hukushima et al., keeping the lowest and highest
+ * fixed and moving the others toward equal replica-exchange acceptance for
+ * every adjacent pair).  One update, host-only: in inverse temperatures
+ * beta_p = 1/temps[p], pair p's new interval is proportional to its old
+ * interval times its acceptance accepted[p] / proposals (floored at half a
+ * swap so no interval collapses), scaled to fill beta_0 - beta_{M-1};
+ * out[0] = temps[0], out[M-1] = temps[M-1], out strictly increasing.
+ * accepted [M-1] (may be NULL for M = 1); out [M] may alias nothing.  Errors:
+ * DA_EINVAL (nulls, M < 1, proposals < 0). */
+int da_pt_ladder_update(int32_t M, const double *temps, const int64_t *accepted,
+                        int64_t proposals, double *out);
+
+/* Adapts a PT ladder on the device: each of `iterations` iterations runs
+ * da_pt's parallel tempering (`chains` chains, `rounds` rounds of
+ * steps_per_round DA steps, random starts, seed + iteration) on the current
+ * ladder, counts every pair's accepted exchanges over all chains and rounds,
+ * and applies da_pt_ladder_update with proposals = chains * rounds.  temps
+ * [M] (host, strictly increasing, > 0) is replaced by the adapted ladder;
+ * acceptance [iterations][M-1] (host, nullable) receives each iteration's
+ * measured acceptances.  Errors: as da_pt, and DA_EINVAL for M < 2 or
+ * rounds < 1. */
+int da_pt_adapt(da_ctx *ctx, double *temps, int32_t M, int32_t chains, int32_t iterations,
+                int64_t rounds, int32_t steps_per_round, int32_t eoff_inc, uint64_t seed,
+                double *acceptance);
 
 /* Exact E(x) = x^T Q x (int64) of `count` host states x [count][N] (uint8,
  * nonzero = 1), computed on the device.  Errors: DA_EINVAL, DA_ENOMEM,
@@ -369,14 +397,17 @@ int da_probe_fields_mfma(int32_t N, int32_t R, int32_t iters, double *ms_per_cal
 /* ---- continuous-batching server ----------------------------------------- */
 typedef struct da_server da_server;
 
-/* One solve request.  Q is copied at submit time. */
+/* One solve request.  Q is copied at submit time.  priority: higher values
+ * are admitted first; a waiting job that does not fit the free budget may
+ * preempt resident jobs of strictly lower priority (0 for all jobs: plain
+ * first-fit admission in submission order, never any preemption). */
 typedef struct da_job {
     const int32_t *Q;
     int32_t N;
     int32_t dtype_hint;
     da_schedule schedule;
     int32_t replicas;
-    int32_t reserved;
+    int32_t priority;
     int64_t steps;
     uint64_t seed;
 } da_job;
@@ -388,7 +419,7 @@ typedef struct da_job_stats {
     double t_done;             /* when its results were on the host          */
     int64_t device_bytes;      /* footprint it was admitted with             */
     int32_t epochs;            /* device epochs it took part in              */
-    int32_t reserved;
+    int32_t preemptions;       /* times it was preempted and re-admitted     */
 } da_job_stats;
 
 /* Server knobs (zero = default). */
@@ -404,11 +435,23 @@ typedef struct da_server_opts {
 int da_server_create(size_t hbm_budget, const da_server_opts *opts, da_server **out);
 
 /* Queue a job; never blocks on the GPU.  A job that does not fit the free
- * budget waits and is admitted as memory frees up.  Results equal those of
- * da_anneal on the same (Q, schedule, replicas, steps, seed), whatever else
- * is running.  Errors: DA_EINVAL, DA_ERANGE, DA_ENOMEM (the job alone exceeds
- * the budget). */
+ * budget waits and is admitted as memory frees up (higher priority first,
+ * then submission order).  When the highest-priority waiting job does not
+ * fit, resident jobs of strictly lower priority are preempted at the next
+ * epoch boundary -- lowest priority, latest admitted first, as many as it
+ * takes -- their state (x, best x, fields, energies, offsets, counts, step)
+ * and coupling matrix copied to host memory and their device memory freed;
+ * a preempted job waits again and, re-admitted, continues from its snapshot.
+ * Results equal those of da_anneal on the same (Q, schedule, replicas, steps,
+ * seed), whatever else is running and however often the job was preempted.
+ * Errors: DA_EINVAL, DA_ERANGE, DA_ENOMEM (the job alone exceeds the budget). */
 int da_submit(da_server *srv, const da_job *job, uint64_t *ticket);
+
+/* Where a job is: state 0 = waiting (being prepared, queued, or preempted),
+ * 1 = resident on the device, 2 = finished (results not yet collected);
+ * done_steps = Monte Carlo steps completed so far (nullable outputs).
+ * Errors: DA_ENOTFOUND (unknown or already collected ticket). */
+int da_job_status(da_server *srv, uint64_t ticket, int32_t *state, int64_t *done_steps);
 
 /* Collect a finished job into host buffers (layouts as da_result, R x N),
  * releasing its ticket.  DA_ENOTREADY if it is still queued or running.

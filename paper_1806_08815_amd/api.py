@@ -72,17 +72,17 @@ class da_batch_item(ctypes.Structure):
 
 class da_pt_result(ctypes.Structure):
     _fields_ = [("best_x", _P), ("best_E", _P), ("final_x", _P), ("final_E", _P),
-                ("n_accept", _P), ("slot", _P), ("n_swaps", _P)]
+                ("n_accept", _P), ("slot", _P), ("n_swaps", _P), ("pair_swaps", _P)]
 
 
 class da_job(ctypes.Structure):
     _fields_ = [("Q", _P), ("N", _i32), ("dtype_hint", _i32), ("schedule", da_schedule),
-                ("replicas", _i32), ("reserved", _i32), ("steps", _i64), ("seed", _u64)]
+                ("replicas", _i32), ("priority", _i32), ("steps", _i64), ("seed", _u64)]
 
 
 class da_job_stats(ctypes.Structure):
     _fields_ = [("t_submit", _dbl), ("t_admit", _dbl), ("t_done", _dbl),
-                ("device_bytes", _i64), ("epochs", _i32), ("reserved", _i32)]
+                ("device_bytes", _i64), ("epochs", _i32), ("preemptions", _i32)]
 
 
 class da_server_opts(ctypes.Structure):
@@ -128,6 +128,8 @@ def lib() -> ctypes.CDLL:
         "da_pt": (_i32, [_P, _P, _i32, _i32, _i64, _i32, _i32, _u64,
                          ctypes.POINTER(da_pt_result)]),
         "da_energy": (_i32, [_P, _P, _i32, _P]),
+        "da_pt_ladder_update": (_i32, [_i32, _P, _P, _i64, _P]),
+        "da_pt_adapt": (_i32, [_P, _P, _i32, _i32, _i32, _i64, _i32, _i32, _u64, _P]),
         "da_last_kernel_stats": (_i32, [_P, ctypes.POINTER(da_kernel_stats)]),
         "da_reset_kernel_stats": (_i32, [_P]),
         "da_last_error": (ctypes.c_char_p, [_P]),
@@ -142,6 +144,8 @@ def lib() -> ctypes.CDLL:
         "da_wait": (_i32, [_P, ctypes.c_uint64, ctypes.POINTER(da_result),
                            ctypes.POINTER(da_job_stats)]),
         "da_job_footprint": (_i64, [_i32, _i32, _i32, _i32]),
+        "da_job_status": (_i32, [_P, ctypes.c_uint64, ctypes.POINTER(_i32),
+                                 ctypes.POINTER(_i64)]),
         "da_server_destroy": (None, [_P]),
         "da_probe_row_stream": (_i32, [_i32, _i32, _i32, _i32, _i32, _i64,
                                        ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)]),
@@ -350,11 +354,33 @@ def da_pt(ctx: Ctx, temps, chains: int, rounds: int, steps_per_round: int, eoff_
     out = _host_outputs(R, ctx.N)
     out["slot"] = np.zeros(R, np.int32)
     out["n_swaps"] = np.zeros(int(chains), np.int64)
+    out["pair_swaps"] = np.zeros((int(chains), max(M - 1, 1)), np.int64)
     res = da_pt_result(*[_ptr(out[k]) for k in ("best_x", "best_E", "final_x", "final_E",
-                                                "n_accept", "slot", "n_swaps")])
+                                                "n_accept", "slot", "n_swaps", "pair_swaps")])
     _check(lib().da_pt(ctx.ptr, _ptr(t), M, int(chains), int(rounds), int(steps_per_round),
                        int(eoff_inc), ctypes.c_uint64(seed), ctypes.byref(res)), ctx.ptr)
+    out["pair_swaps"] = out["pair_swaps"][:, :max(M - 1, 0)]
     return out
+
+
+def da_pt_ladder_update(temps, accepted, proposals: int) -> np.ndarray:
+    t = np.ascontiguousarray(np.asarray(temps, dtype=np.float64))
+    a = np.ascontiguousarray(np.asarray(accepted, dtype=np.int64))
+    out = np.zeros_like(t)
+    _check(lib().da_pt_ladder_update(t.shape[0], _ptr(t), _ptr(a), int(proposals), _ptr(out)))
+    return out
+
+
+def da_pt_adapt(ctx: Ctx, temps, chains: int, iterations: int, rounds: int,
+                steps_per_round: int, eoff_inc: int, seed: int):
+    """(adapted ladder, acceptances [iterations][M-1])."""
+    t = np.ascontiguousarray(np.asarray(temps, dtype=np.float64)).copy()
+    M = t.shape[0]
+    acc = np.zeros((int(iterations), max(M - 1, 1)))
+    _check(lib().da_pt_adapt(ctx.ptr, _ptr(t), M, int(chains), int(iterations), int(rounds),
+                             int(steps_per_round), int(eoff_inc), ctypes.c_uint64(seed),
+                             _ptr(acc)), ctx.ptr)
+    return t, acc[:, :max(M - 1, 0)]
 
 
 def da_energy(ctx: Ctx, x) -> np.ndarray:
@@ -434,10 +460,10 @@ def da_server_create(hbm_budget: int, epoch_steps: int = 0, max_resident: int = 
 
 
 def da_submit(srv: Server, Q, sched: da_schedule, replicas: int, steps: int, seed: int,
-              dtype_hint: int = DA_DTYPE_AUTO) -> int:
+              dtype_hint: int = DA_DTYPE_AUTO, priority: int = 0) -> int:
     Q = np.ascontiguousarray(np.asarray(Q, dtype=np.int32))
-    job = da_job(_ptr(Q), Q.shape[0], int(dtype_hint), sched, int(replicas), 0, int(steps),
-                 ctypes.c_uint64(seed).value)
+    job = da_job(_ptr(Q), Q.shape[0], int(dtype_hint), sched, int(replicas), int(priority),
+                 int(steps), ctypes.c_uint64(seed).value)
     t = ctypes.c_uint64()
     _check(lib().da_submit(srv.ptr, ctypes.byref(job), ctypes.byref(t)))
     srv._jobs[t.value] = (int(replicas), Q.shape[0])
@@ -467,6 +493,15 @@ def da_poll(srv: Server, ticket: int):
 
 def da_wait(srv: Server, ticket: int) -> dict:
     return _collect(lib().da_wait, srv, ticket)
+
+
+def da_job_status(srv: Server, ticket: int) -> tuple[int, int]:
+    """(state, done_steps): state 0 waiting, 1 resident, 2 finished."""
+    st = _i32()
+    done = _i64()
+    _check(lib().da_job_status(srv.ptr, ctypes.c_uint64(ticket), ctypes.byref(st),
+                               ctypes.byref(done)))
+    return int(st.value), int(done.value)
 
 
 def da_job_footprint(N: int, dtype_bytes: int, replicas: int, n_levels: int) -> int:

@@ -900,7 +900,8 @@ void da_destroy(da_ctx *ctx) {
     if (ctx->d_b) (void)hipFree(ctx->d_b);
     if (ctx->d_ell) (void)hipFree(ctx->d_ell);
     for (void *p : {(void *)ctx->pt_slot2rep, (void *)ctx->pt_lvl, (void *)ctx->pt_swaps,
-                    (void *)ctx->pt_round, (void *)ctx->pt_dbeta, (void *)ctx->pt_lnU})
+                    (void *)ctx->pt_pair, (void *)ctx->pt_round, (void *)ctx->pt_dbeta,
+                    (void *)ctx->pt_lnU})
         if (p) (void)hipFree(p);
     for (auto &pr : ctx->ev_pool) {
         (void)hipEventDestroy(pr.first);
@@ -1160,9 +1161,12 @@ int da_anneal_batch(const da_batch_item *items, int32_t count, void *stream) {
     return DA_OK;
 }
 
-int da_pt(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t rounds,
-          int32_t steps_per_round, int32_t eoff_inc, uint64_t seed, da_pt_result *out) {
-    if (!ctx) return fail(nullptr, DA_EINVAL, "ctx is null");
+}  // extern "C"
+
+namespace {
+
+int check_pt_args(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t rounds,
+                  int32_t steps_per_round, int32_t eoff_inc) {
     if (!temps || M < 1 || M > kMaxLevels || chains < 1 || rounds < 0 || steps_per_round < 0 ||
         eoff_inc < 0)
         return fail(ctx, DA_EINVAL, "bad PT arguments");
@@ -1175,7 +1179,15 @@ int da_pt(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t r
         if (p + 1 < M && !(temps[p] < temps[p + 1]))
             return fail(ctx, DA_EINVAL, "temperatures must be strictly increasing");
     }
+    return DA_OK;
+}
+
+// One PT run on the device (arguments already checked): random starts, then
+// `rounds` rounds of steps_per_round DA steps and an exchange sweep.
+int pt_run(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t rounds,
+           int32_t steps_per_round, int32_t eoff_inc, uint64_t seed, da_pt_result *out) {
     const int32_t R = M * chains;
+    const int32_t npair = chains * std::max(M - 1, 1);
     std::string err;
     std::vector<double> tv(temps, temps + M);
     auto lt = get_level_tables(tv, err);
@@ -1185,25 +1197,29 @@ int da_pt(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t r
     if (!ctx->st.ensure(R, ctx->ld, err)) return fail(ctx, DA_ENOMEM, err);
     hipStream_t s = ctx->own_stream;
     int rc = DA_OK;
-    if (R > ctx->pt_cap_R || M > ctx->pt_cap_M || chains > ctx->pt_cap_chains) {
+    if (R > ctx->pt_cap_R || M > ctx->pt_cap_M || chains > ctx->pt_cap_chains ||
+        npair > ctx->pt_cap_pairs) {
         for (void *p : {(void *)ctx->pt_slot2rep, (void *)ctx->pt_lvl, (void *)ctx->pt_swaps,
-                        (void *)ctx->pt_round, (void *)ctx->pt_dbeta, (void *)ctx->pt_lnU})
+                        (void *)ctx->pt_pair, (void *)ctx->pt_round, (void *)ctx->pt_dbeta,
+                        (void *)ctx->pt_lnU})
             if (p) (void)hipFree(p);
         ctx->pt_slot2rep = ctx->pt_lvl = nullptr;
-        ctx->pt_swaps = nullptr;
+        ctx->pt_swaps = ctx->pt_pair = nullptr;
         ctx->pt_round = nullptr;
         ctx->pt_dbeta = ctx->pt_lnU = nullptr;
-        ctx->pt_cap_R = ctx->pt_cap_M = ctx->pt_cap_chains = 0;
+        ctx->pt_cap_R = ctx->pt_cap_M = ctx->pt_cap_chains = ctx->pt_cap_pairs = 0;
         rc = check_hip(ctx, hipMalloc(&ctx->pt_slot2rep, (size_t)R * 4), "PT allocation");
         if (!rc) rc = check_hip(ctx, hipMalloc(&ctx->pt_lvl, (size_t)R * 4), "PT allocation");
         if (!rc) rc = check_hip(ctx, hipMalloc(&ctx->pt_swaps, (size_t)chains * 8), "PT allocation");
-        if (!rc) rc = check_hip(ctx, hipMalloc(&ctx->pt_round, 4), "PT allocation");
+        if (!rc) rc = check_hip(ctx, hipMalloc(&ctx->pt_pair, (size_t)npair * 8), "PT allocation");
+        if (!rc) rc = check_hip(ctx, hipMalloc(&ctx->pt_round, 8), "PT allocation");
         if (!rc) rc = check_hip(ctx, hipMalloc(&ctx->pt_dbeta, (size_t)M * 8), "PT allocation");
         if (!rc) rc = check_hip(ctx, hipMalloc(&ctx->pt_lnU, 65536 * 8), "PT allocation");
         if (rc) return rc;
         ctx->pt_cap_R = R;
         ctx->pt_cap_M = M;
         ctx->pt_cap_chains = chains;
+        ctx->pt_cap_pairs = npair;
     }
     // exchange tables: 1/T_p - 1/T_{p+1} and ln U_u, U_u = (u + 1/2)/65536
     std::vector<double> dbeta((size_t)M, 0.0), lnU(65536);
@@ -1223,7 +1239,11 @@ int da_pt(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t r
     J.K = steps_per_round;
     if (const char *why = job_range_error(J)) return fail(ctx, DA_EINVAL, why);
     rc = init_state(ctx, J, DA_INIT_RANDOM, s);
-    if (!rc) rc = check_hip(ctx, (hipError_t)launch_pt_setup(ctx->pt_slot2rep, ctx->pt_lvl, ctx->pt_swaps, ctx->pt_round, M, chains, s), "PT setup");
+    if (!rc)
+        rc = check_hip(ctx, (hipError_t)launch_pt_setup(ctx->pt_slot2rep, ctx->pt_lvl,
+                                                        ctx->pt_swaps, ctx->pt_pair,
+                                                        ctx->pt_round, M, chains, s),
+                       "PT setup");
     hipEvent_t pe0 = nullptr, pe1 = nullptr;
     if (!rc) rc = next_events(ctx, pe0, pe1);
     if (!rc) rc = check_hip(ctx, hipEventRecord(pe0, s), "event record");
@@ -1234,8 +1254,8 @@ int da_pt(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t r
         if (steps_per_round > 0)
             e = launch_run(J, sh.F, sh.NH > 0, nullptr, sh.blocks, sh.threads, sh.lds, s);
         if (!e)
-            e = launch_pt_exchange(J.E, ctx->pt_slot2rep, ctx->pt_lvl, ctx->pt_dbeta, ctx->pt_lnU, M,
-                                   chains, seed, ctx->pt_round, ctx->pt_swaps, s);
+            e = launch_pt_exchange(J.E, ctx->pt_slot2rep, ctx->pt_lvl, ctx->pt_dbeta, ctx->pt_lnU,
+                                   M, chains, seed, ctx->pt_round, ctx->pt_swaps, ctx->pt_pair, s);
         return e;
     };
     // Rounds are captured into a hipGraph (kernels only, no memsets) and
@@ -1268,11 +1288,85 @@ int da_pt(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t r
         if (!rc && out->slot) e = hipMemcpy(out->slot, ctx->pt_lvl, (size_t)R * 4, hipMemcpyDeviceToHost);
         if (e == hipSuccess && !rc && out->n_swaps)
             e = hipMemcpy(out->n_swaps, ctx->pt_swaps, (size_t)chains * 8, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && !rc && out->pair_swaps && M > 1)
+            e = hipMemcpy(out->pair_swaps, ctx->pt_pair, (size_t)chains * (M - 1) * 8,
+                          hipMemcpyDeviceToHost);
         if (!rc) rc = check_hip(ctx, e, "PT output copy");
     } else {
         rc = check_hip(ctx, hipStreamSynchronize(s), "stream synchronise");
     }
     return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int da_pt(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t rounds,
+          int32_t steps_per_round, int32_t eoff_inc, uint64_t seed, da_pt_result *out) {
+    if (!ctx) return fail(nullptr, DA_EINVAL, "ctx is null");
+    const int rc = check_pt_args(ctx, temps, M, chains, rounds, steps_per_round, eoff_inc);
+    if (rc) return rc;
+    return pt_run(ctx, temps, M, chains, rounds, steps_per_round, eoff_inc, seed, out);
+}
+
+int da_pt_ladder_update(int32_t M, const double *temps, const int64_t *accepted,
+                        int64_t proposals, double *out) {
+    if (!temps || !out || (M > 1 && !accepted) || M < 1 || proposals < 0)
+        return fail(nullptr, DA_EINVAL, "bad ladder-update arguments");
+    for (int p = 0; p < M; ++p) out[p] = temps[p];
+    if (M < 3 || proposals < 1) return DA_OK;
+    // in inverse temperature: the span beta_0 - beta_{M-1} stays, and each
+    // pair's interval becomes proportional to (its interval) * (its
+    // acceptance, floored at half a swap), so more-accepting pairs widen
+    const double beta_cold = 1.0 / temps[0];
+    const double beta_hot = 1.0 / temps[M - 1];
+    const double floor_acc = 0.5 / (double)proposals;
+    std::vector<double> w((size_t)M - 1);
+    double total = 0.0;
+    for (int p = 0; p + 1 < M; ++p) {
+        double a = (double)accepted[p] / (double)proposals;
+        if (a < floor_acc) a = floor_acc;
+        w[(size_t)p] = (1.0 / temps[p] - 1.0 / temps[p + 1]) * a;
+        total += w[(size_t)p];
+    }
+    double beta = beta_cold;
+    for (int p = 0; p + 2 < M; ++p) {
+        beta = beta - (beta_cold - beta_hot) * (w[(size_t)p] / total);
+        out[p + 1] = 1.0 / beta;
+    }
+    return DA_OK;
+}
+
+int da_pt_adapt(da_ctx *ctx, double *temps, int32_t M, int32_t chains, int32_t iterations,
+                int64_t rounds, int32_t steps_per_round, int32_t eoff_inc, uint64_t seed,
+                double *acceptance) {
+    if (!ctx) return fail(nullptr, DA_EINVAL, "ctx is null");
+    if (M < 2 || iterations < 0 || rounds < 1)
+        return fail(ctx, DA_EINVAL, "ladder adaptation needs M >= 2, rounds >= 1");
+    int rc = check_pt_args(ctx, temps, M, chains, rounds, steps_per_round, eoff_inc);
+    if (rc) return rc;
+    std::vector<int64_t> ps((size_t)chains * (M - 1)), acc((size_t)M - 1);
+    std::vector<double> next((size_t)M);
+    const int64_t proposals = (int64_t)chains * rounds;
+    for (int32_t it = 0; it < iterations; ++it) {
+        da_pt_result o{};
+        o.pair_swaps = ps.data();
+        rc = pt_run(ctx, temps, M, chains, rounds, steps_per_round, eoff_inc,
+                    seed + (uint64_t)it, &o);
+        if (rc) return rc;
+        for (int p = 0; p + 1 < M; ++p) {
+            int64_t a = 0;
+            for (int32_t c = 0; c < chains; ++c) a += ps[(size_t)c * (M - 1) + p];
+            acc[(size_t)p] = a;
+            if (acceptance)
+                acceptance[(size_t)it * (M - 1) + p] = (double)a / (double)proposals;
+        }
+        rc = da_pt_ladder_update(M, temps, acc.data(), proposals, next.data());
+        if (rc) return rc;
+        for (int p = 0; p < M; ++p) temps[p] = next[(size_t)p];
+    }
+    return DA_OK;
 }
 
 int da_energy(da_ctx *ctx, const uint8_t *x, int32_t count, int64_t *E) {

@@ -158,11 +158,16 @@ int launch_run(const JobDesc &J, int F, bool help, const TraceDesc *trace, int b
 int launch_batch(const JobDesc *jobs_dev, const BatchItem *items_dev, const int32_t *n_items_dev,
                  int32_t *counter_dev, int blocks, int threads, size_t lds_bytes, void *stream,
                  bool dynamic);
+// Exchange sweep of every chain (one workgroup per chain, M <= 4096); round
+// points to two words: the round index and a count of the workgroups that
+// have read it.  pair_swaps [chains][M-1] counts accepted exchanges per pair.
 int launch_pt_exchange(int64_t *E, int32_t *slot2rep, int32_t *lvl_of_rep, const double *dbeta,
                        const double *lnU, int32_t M, int32_t chains, uint64_t seed,
-                       uint32_t *round_ptr, int64_t *n_swaps, void *stream);
+                       uint32_t *round_ptr, int64_t *n_swaps, int64_t *pair_swaps,
+                       void *stream);
 int launch_pt_setup(int32_t *slot2rep, int32_t *lvl_of_rep, int64_t *n_swaps,
-                    uint32_t *round_ptr, int32_t M, int32_t chains, void *stream);
+                    int64_t *pair_swaps, uint32_t *round_ptr, int32_t M, int32_t chains,
+                    void *stream);
 int launch_extract(const JobDesc &J, const uint8_t *src_x, uint8_t *dst_x, int32_t R,
                    void *stream);
 int launch_copy_i64(const int64_t *src, int64_t *dst, int32_t n, void *stream);

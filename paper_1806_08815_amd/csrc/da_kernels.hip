@@ -27,6 +27,7 @@
 //     updates its fields.  W stays in L2 / MALL / HBM, or in LDS when small.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <type_traits>
 
@@ -1148,43 +1149,91 @@ __global__ __launch_bounds__(256) void k_energy_from_fields(const uint8_t *__res
 // Parallel tempering: replica exchange on the device (Algorithm 3's exchange
 // move; Sec. II.D notes the next DA generation moves it off the host).
 // slot2rep[c*M + p] is the replica (0..M-1) at temperature p of chain c.
+// One workgroup of 64 lanes per chain: the lanes draw the M-1 exchange
+// numbers and look up ln U of each at once, then one lane walks the pairs in
+// ascending order (each decision depends on the swaps before it), and the
+// lanes write the new slots back.  round[0] is the round index every kernel
+// of the round reads; round[1] counts the workgroups that have read it, and
+// the last of them advances round[0] (no workgroup waits for another).
 // --------------------------------------------------------------------------
-__global__ void k_pt_exchange(const int64_t *__restrict__ E, int32_t *slot2rep,
-                              int32_t *lvl_of_rep, const double *__restrict__ dbeta,
-                              const double *__restrict__ lnU, int32_t M, int32_t chains,
-                              uint64_t seed, uint32_t *round_ptr, int64_t *n_swaps) {
-    const uint32_t t = *round_ptr;
+constexpr int kPtMaxM = 4096;
+
+__global__ __launch_bounds__(64) void k_pt_exchange(const int64_t *__restrict__ E,
+                                                    int32_t *slot2rep, int32_t *lvl_of_rep,
+                                                    const double *__restrict__ dbeta,
+                                                    const double *__restrict__ lnU, int32_t M,
+                                                    int32_t chains, uint64_t seed,
+                                                    uint32_t *round, int64_t *n_swaps,
+                                                    int64_t *pair_swaps) {
+    __shared__ double lnu[kPtMaxM];
+    __shared__ int32_t s2r[kPtMaxM];
+    __shared__ uint32_t t_sh;
+    const int c = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (lane == 0) {
+        const uint32_t t = *(volatile uint32_t *)round;
+        t_sh = t;
+        __threadfence();
+        // the last workgroup to have read the round index advances it
+        if (atomicAdd(&round[1], 1u) == (uint32_t)chains - 1u) {
+            round[1] = 0u;
+            __threadfence();
+            *(volatile uint32_t *)round = t + 1u;
+        }
+    }
+    __syncthreads();
+    const uint32_t t = t_sh;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    for (int c = threadIdx.x; c < chains; c += blockDim.x) {
-        int32_t *s2r = slot2rep + (size_t)c * M;
+    int32_t *gs2r = slot2rep + (size_t)c * M;
+    for (int p = lane; p < M; p += 64) {
+        s2r[p] = gs2r[p];
+        if (p + 1 < M) {
+            const uint32_t u =
+                philox((uint32_t)p, t, (uint32_t)c, kTagExchange, k0, k1).x & 0xFFFFu;
+            lnu[p] = lnU[u];
+        }
+    }
+    __syncthreads();
+    if (lane == 0) {
+        const int64_t *Ec = E + (size_t)c * M;
+        int64_t *ps = pair_swaps + (size_t)c * (M > 1 ? M - 1 : 1);
         int64_t sw = 0;
         for (int p = 0; p + 1 < M; ++p) {
             const int a = s2r[p], bq = s2r[p + 1];
-            const double diff = (double)(E[(size_t)c * M + a] - E[(size_t)c * M + bq]);
+            const double diff = (double)(Ec[a] - Ec[bq]);
             const double delta = __dmul_rn(dbeta[p], diff);
-            const uint32_t u = philox((uint32_t)p, t, (uint32_t)c, kTagExchange, k0, k1).x & 0xFFFFu;
-            if (lnU[u] < delta) {
+            if (lnu[p] < delta) {
                 s2r[p] = bq;
                 s2r[p + 1] = a;
                 ++sw;
+                ps[p] += 1;
             }
         }
         n_swaps[c] += sw;
-        for (int p = 0; p < M; ++p) lvl_of_rep[(size_t)c * M + s2r[p]] = p;
     }
     __syncthreads();
-    if (threadIdx.x == 0) *round_ptr = t + 1;
+    for (int p = lane; p < M; p += 64) {
+        gs2r[p] = s2r[p];
+        lvl_of_rep[(size_t)c * M + s2r[p]] = p;
+    }
 }
 
 __global__ void k_pt_setup(int32_t *slot2rep, int32_t *lvl_of_rep, int64_t *n_swaps,
-                           uint32_t *round_ptr, int32_t M, int32_t chains) {
-    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < M * chains;
+                           int64_t *pair_swaps, uint32_t *round, int32_t M, int32_t chains) {
+    const int npair = chains * (M > 1 ? M - 1 : 1);
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < M * chains || q < npair;
          q += gridDim.x * blockDim.x) {
-        slot2rep[q] = q % M;
-        lvl_of_rep[q] = q % M;
+        if (q < M * chains) {
+            slot2rep[q] = q % M;
+            lvl_of_rep[q] = q % M;
+        }
         if (q < chains) n_swaps[q] = 0;
+        if (q < npair) pair_swaps[q] = 0;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) *round_ptr = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        round[0] = 0u;
+        round[1] = 0u;
+    }
 }
 
 // Copy [R][ld] state rows to dense [R][N] output rows.
@@ -1388,17 +1437,20 @@ int launch_energy_from_fields(const JobDesc &J, const uint8_t *X, const int32_t 
 
 int launch_pt_exchange(int64_t *E, int32_t *slot2rep, int32_t *lvl_of_rep, const double *dbeta,
                        const double *lnU, int32_t M, int32_t chains, uint64_t seed,
-                       uint32_t *round_ptr, int64_t *n_swaps, void *stream) {
-    int threads = chains < 64 ? 64 : (chains > 1024 ? 1024 : ((chains + 63) / 64) * 64);
-    hipLaunchKernelGGL(k_pt_exchange, dim3(1), dim3(threads), 0, S(stream), E, slot2rep,
-                       lvl_of_rep, dbeta, lnU, M, chains, seed, round_ptr, n_swaps);
+                       uint32_t *round_ptr, int64_t *n_swaps, int64_t *pair_swaps,
+                       void *stream) {
+    if (M < 1 || M > kPtMaxM || chains < 1) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pt_exchange, dim3(chains), dim3(64), 0, S(stream), E, slot2rep,
+                       lvl_of_rep, dbeta, lnU, M, chains, seed, round_ptr, n_swaps, pair_swaps);
     return (int)hipGetLastError();
 }
 
 int launch_pt_setup(int32_t *slot2rep, int32_t *lvl_of_rep, int64_t *n_swaps,
-                    uint32_t *round_ptr, int32_t M, int32_t chains, void *stream) {
-    hipLaunchKernelGGL(k_pt_setup, dim3(grid_for((int64_t)M * chains, 256)), dim3(256), 0,
-                       S(stream), slot2rep, lvl_of_rep, n_swaps, round_ptr, M, chains);
+                    int64_t *pair_swaps, uint32_t *round_ptr, int32_t M, int32_t chains,
+                    void *stream) {
+    const int64_t n = std::max<int64_t>((int64_t)M * chains, (int64_t)chains * std::max(M - 1, 1));
+    hipLaunchKernelGGL(k_pt_setup, dim3(grid_for(n, 256)), dim3(256), 0, S(stream), slot2rep,
+                       lvl_of_rep, n_swaps, pair_swaps, round_ptr, M, chains);
     return (int)hipGetLastError();
 }
 

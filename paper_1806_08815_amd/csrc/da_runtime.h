@@ -186,9 +186,10 @@ struct da_ctx {
     // PT scratch
     int32_t *pt_slot2rep = nullptr, *pt_lvl = nullptr;
     int64_t *pt_swaps = nullptr;
-    uint32_t *pt_round = nullptr;
+    int64_t *pt_pair = nullptr;      // accepted exchanges [chains][M-1]
+    uint32_t *pt_round = nullptr;    // [2]: round index, workgroups that read it
     double *pt_dbeta = nullptr, *pt_lnU = nullptr;
-    int32_t pt_cap_R = 0, pt_cap_M = 0, pt_cap_chains = 0;
+    int32_t pt_cap_R = 0, pt_cap_M = 0, pt_cap_chains = 0, pt_cap_pairs = 0;
     std::shared_ptr<dapt::LevelTables> keep_tables;
     std::shared_ptr<dapt::StepTables> keep_steps;
     // what the replica state in `st` holds: replicas st_base .. st_base+st_R-1

@@ -12,13 +12,17 @@
 //     step kernel (replayed from a captured graph);
 //   * retirement: after an epoch, jobs that reached their step count are
 //     copied to host buffers and their device memory is released, which lets
-//     waiting jobs in.
+//     waiting jobs in;
+//   * preemption: when the highest-priority waiting job does not fit, resident
+//     jobs of lower priority are snapshotted to host memory between epochs and
+//     released; they queue again and resume from the snapshot when re-admitted.
 // The step kernel resumes exactly where an epoch stopped and every random
 // number is keyed by (seed, job-local replica id, global step), so a job's
 // results are the same alone, in any mix, and as a plain da_anneal call.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -50,7 +54,13 @@ struct Job {
     da_ctx *ctx = nullptr;
     std::shared_ptr<LevelTables> tables;
     JobDesc J{};
-    int64_t done_steps = 0;
+    std::atomic<int64_t> done_steps{0};   // written by the worker, read by status queries
+    int32_t priority = 0;
+    // a preempted job's replica state (host), restored when it is re-admitted
+    bool preempted = false;
+    std::vector<uint8_t> snap_x, snap_bx;
+    std::vector<int32_t> snap_h, snap_eoff;
+    std::vector<int64_t> snap_E, snap_bE, snap_nacc;
     int status = DA_OK;
     std::string err;
     // results
@@ -79,6 +89,7 @@ struct da_server {
     std::vector<std::unique_ptr<Job>> resident;
     std::map<uint64_t, std::unique_ptr<Job>> finished;
     std::set<uint64_t> retiring;   // left `resident`, results being copied out
+    std::set<uint64_t> preempting; // left `resident`, state being copied out
     uint64_t next_ticket = 1;
     int64_t used = 0;
     bool stop = false;
@@ -93,6 +104,9 @@ struct da_server {
     bool admit_locked(std::vector<Job *> &admitted);
     int start_job(Job &j);
     void retire(std::unique_ptr<Job> &j);
+    void pick_victims_locked(std::vector<std::unique_ptr<Job>> &victims);
+    void preempt(Job &j);
+    void enqueue_locked(std::unique_ptr<Job> jp);
     bool known_locked(uint64_t ticket) const;
     uint64_t first_unprepared_locked() const {
         uint64_t t = UINT64_MAX;
@@ -102,8 +116,15 @@ struct da_server {
     }
     // something the device worker can do now
     bool has_work_locked() const {
-        return stop || !resident.empty() ||
-               (!queue.empty() && queue.front()->ticket < first_unprepared_locked());
+        if (stop || !resident.empty()) return true;
+        const uint64_t fu = first_unprepared_locked();
+        for (auto &q : queue)
+            if (q->ticket < fu) return true;
+        return false;
+    }
+    // queue order: higher priority first, then submission order
+    static bool before(const Job &a, const Job &b) {
+        return a.priority != b.priority ? a.priority > b.priority : a.ticket < b.ticket;
     }
 };
 
@@ -140,13 +161,18 @@ void da_server::prep_loop() {
         {
             std::lock_guard<std::mutex> lock(mu);
             preparing.erase(j.ticket);
-            auto pos = std::upper_bound(
-                queue.begin(), queue.end(), j.ticket,
-                [](uint64_t t, const std::unique_ptr<Job> &q) { return t < q->ticket; });
-            queue.insert(pos, std::move(jp));
+            enqueue_locked(std::move(jp));
         }
         cv_work.notify_one();
     }
+}
+
+void da_server::enqueue_locked(std::unique_ptr<Job> jp) {
+    auto pos = std::upper_bound(queue.begin(), queue.end(), jp,
+                                [](const std::unique_ptr<Job> &a, const std::unique_ptr<Job> &b) {
+                                    return before(*a, *b);
+                                });
+    queue.insert(pos, std::move(jp));
 }
 
 // Device context, tables and initial state of an admitted job, on the upload
@@ -157,6 +183,7 @@ int da_server::start_job(Job &j) {
     HostMatrix().W.swap(j.hm.W);
     if (rc) return rc;
     j.ctx = ctx;
+    // (a re-admitted job's tables come from the cache, or are built again)
     j.tables = get_level_tables(schedule_temps(j.spec.schedule), j.err, j.ht.get());
     j.ht.reset();
     if (!j.tables) return DA_ENOMEM;
@@ -165,9 +192,118 @@ int da_server::start_job(Job &j) {
     const LaunchShape sh = batch_shape(ctx);
     j.J = make_job(ctx, *j.tables, j.spec.replicas, 0u, j.spec.seed, j.spec.steps,
                    j.spec.schedule, sh);
-    rc = init_state(ctx, j.J, j.spec.schedule.init, upload);
-    if (rc) j.err = ctx->err;
-    return rc;
+    if (const char *why = job_range_error(j.J)) {
+        j.err = why;
+        return DA_EINVAL;
+    }
+    if (!j.preempted) {
+        rc = init_state(ctx, j.J, j.spec.schedule.init, upload);
+        if (rc) j.err = ctx->err;
+        return rc;
+    }
+    // continue from the snapshot (the host copies live until the upload
+    // stream is synchronised, before the job's next epoch)
+    const size_t R = (size_t)j.spec.replicas, rows = R * (size_t)j.J.ld;
+    hipError_t e = hipMemcpyAsync(j.J.x, j.snap_x.data(), rows, hipMemcpyHostToDevice, upload);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(j.J.bx, j.snap_bx.data(), rows, hipMemcpyHostToDevice, upload);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(j.J.h, j.snap_h.data(), rows * 4, hipMemcpyHostToDevice, upload);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(j.J.E, j.snap_E.data(), R * 8, hipMemcpyHostToDevice, upload);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(j.J.bE, j.snap_bE.data(), R * 8, hipMemcpyHostToDevice, upload);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(j.J.nacc, j.snap_nacc.data(), R * 8, hipMemcpyHostToDevice, upload);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(j.J.eoff, j.snap_eoff.data(), R * 4, hipMemcpyHostToDevice, upload);
+    if (e != hipSuccess) {
+        j.err = std::string("snapshot upload: ") + hipGetErrorString(e);
+        return DA_EDEVICE;
+    }
+    return DA_OK;
+}
+
+// Resident jobs to send back to the queue so that the highest-priority
+// waiting job fits: strictly lower priority only, lowest priority and then
+// latest admitted first, and only if enough of them free enough room.
+void da_server::pick_victims_locked(std::vector<std::unique_ptr<Job>> &victims) {
+    const uint64_t fu = first_unprepared_locked();
+    Job *head = nullptr;
+    for (auto &q : queue)
+        if (q->ticket < fu) {
+            head = q.get();
+            break;
+        }
+    if (!head) return;
+    auto fits = [&](int64_t freed, size_t leaving) {
+        const bool mem = head->footprint <= (int64_t)budget - used + freed;
+        const bool slots = max_resident <= 0 ||
+                           (int64_t)resident.size() - (int64_t)leaving < (int64_t)max_resident;
+        return mem && slots;
+    };
+    if (fits(0, 0)) return;   // it is admitted on the next pass
+    std::vector<size_t> cand;
+    for (size_t i = 0; i < resident.size(); ++i)
+        if (resident[i]->priority < head->priority && resident[i]->status == DA_OK &&
+            resident[i]->done_steps < resident[i]->spec.steps)
+            cand.push_back(i);
+    std::stable_sort(cand.begin(), cand.end(), [&](size_t a, size_t b) {
+        const Job &x = *resident[a], &y = *resident[b];
+        if (x.priority != y.priority) return x.priority < y.priority;
+        return x.stats.t_admit > y.stats.t_admit;
+    });
+    int64_t freed = 0;
+    size_t n = 0;
+    while (n < cand.size() && !fits(freed, n)) freed += resident[cand[n++]]->footprint;
+    if (!fits(freed, n)) return;   // even all of them would not make room
+    std::vector<size_t> take(cand.begin(), cand.begin() + (ptrdiff_t)n);
+    std::sort(take.rbegin(), take.rend());   // erase from the back
+    for (size_t i : take) {
+        preempting.insert(resident[i]->ticket);
+        victims.push_back(std::move(resident[i]));
+        resident.erase(resident.begin() + (ptrdiff_t)i);
+    }
+}
+
+// Copies a resident job's replica state and coupling matrix to host memory
+// and frees its device memory (no epoch is in flight when this runs).
+void da_server::preempt(Job &j) {
+    da_ctx *ctx = j.ctx;
+    const size_t R = (size_t)j.spec.replicas, ld = (size_t)j.J.ld, rows = R * ld;
+    j.snap_x.resize(rows);
+    j.snap_bx.resize(rows);
+    j.snap_h.resize(rows);
+    j.snap_E.resize(R);
+    j.snap_bE.resize(R);
+    j.snap_nacc.resize(R);
+    j.snap_eoff.resize(R);
+    j.hm.W.resize(ld * ld * (size_t)ctx->dtype);
+    hipError_t e = hipMemcpyAsync(j.snap_x.data(), j.J.x, rows, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(j.snap_bx.data(), j.J.bx, rows, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(j.snap_h.data(), j.J.h, rows * 4, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(j.snap_E.data(), j.J.E, R * 8, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(j.snap_bE.data(), j.J.bE, R * 8, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(j.snap_nacc.data(), j.J.nacc, R * 8, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(j.snap_eoff.data(), j.J.eoff, R * 4, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(j.hm.W.data(), ctx->d_W, j.hm.W.size(), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        j.status = DA_EDEVICE;
+        j.err = std::string("preemption snapshot: ") + hipGetErrorString(e);
+    }
+    da_destroy(ctx);
+    j.ctx = nullptr;
+    j.tables.reset();
+    j.preempted = true;
+    j.stats.preemptions += 1;
 }
 
 bool da_server::admit_locked(std::vector<Job *> &admitted) {
@@ -175,7 +311,10 @@ bool da_server::admit_locked(std::vector<Job *> &admitted) {
     // submission order: a job never overtakes an earlier one still being prepared
     const uint64_t first_unprepared = first_unprepared_locked();
     for (auto it = queue.begin(); it != queue.end();) {
-        if ((*it)->ticket > first_unprepared) break;
+        if ((*it)->ticket > first_unprepared) {
+            ++it;
+            continue;
+        }
         if (max_resident > 0 && (int32_t)(resident.size() + admitted.size()) >= max_resident) break;
         if ((*it)->footprint <= (int64_t)budget - used) {
             used += (*it)->footprint;
@@ -220,6 +359,9 @@ void da_server::retire(std::unique_ptr<Job> &jp) {
     if (j.ctx) da_destroy(j.ctx);
     j.ctx = nullptr;
     j.tables.reset();
+    for (auto *v : {&j.snap_x, &j.snap_bx}) std::vector<uint8_t>().swap(*v);
+    for (auto *v : {&j.snap_h, &j.snap_eoff}) std::vector<int32_t>().swap(*v);
+    for (auto *v : {&j.snap_E, &j.snap_bE, &j.snap_nacc}) std::vector<int64_t>().swap(*v);
     j.stats.t_done = now_s(t0);
 }
 
@@ -283,12 +425,18 @@ void da_server::run() {
         }
         if (!admitted.empty()) {
             const hipError_t e = hipStreamSynchronize(upload);
-            if (e != hipSuccess)
-                for (Job *j : admitted)
-                    if (j->status == DA_OK) {
-                        j->status = DA_EDEVICE;
-                        j->err = hipGetErrorString(e);
-                    }
+            for (Job *j : admitted) {
+                if (e != hipSuccess && j->status == DA_OK) {
+                    j->status = DA_EDEVICE;
+                    j->err = hipGetErrorString(e);
+                }
+                // a re-admitted job's snapshot is on the device now
+                for (auto *v : {&j->snap_x, &j->snap_bx}) std::vector<uint8_t>().swap(*v);
+                for (auto *v : {&j->snap_h, &j->snap_eoff}) std::vector<int32_t>().swap(*v);
+                for (auto *v : {&j->snap_E, &j->snap_bE, &j->snap_nacc})
+                    std::vector<int64_t>().swap(*v);
+                j->preempted = false;
+            }
         }
         // retire finished (or failed) jobs and wake their waiters
         std::vector<std::unique_ptr<Job>> leaving;
@@ -313,6 +461,32 @@ void da_server::run() {
                     const uint64_t t = jp->ticket;
                     retiring.erase(t);
                     finished[t] = std::move(jp);
+                }
+            }
+            cv_done.notify_all();
+        }
+        // preemption (no epoch in flight here): lower-priority resident jobs
+        // make room for the highest-priority waiting job that does not fit;
+        // it is admitted on the next pass, while the next epoch runs
+        std::vector<std::unique_ptr<Job>> victims;
+        if (!stop) {
+            std::lock_guard<std::mutex> lock(mu);
+            pick_victims_locked(victims);
+        }
+        for (auto &vp : victims) preempt(*vp);
+        if (!victims.empty()) {
+            {
+                std::lock_guard<std::mutex> lock(mu);
+                for (auto &vp : victims) {
+                    used -= vp->footprint;
+                    preempting.erase(vp->ticket);
+                    if (vp->status != DA_OK) {
+                        vp->stats.t_done = now_s(t0);
+                        const uint64_t t = vp->ticket;
+                        finished[t] = std::move(vp);
+                    } else {
+                        enqueue_locked(std::move(vp));
+                    }
                 }
             }
             cv_done.notify_all();
@@ -350,7 +524,9 @@ void da_server::run() {
 }
 
 bool da_server::known_locked(uint64_t ticket) const {
-    if (finished.count(ticket) || retiring.count(ticket) || preparing.count(ticket)) return true;
+    if (finished.count(ticket) || retiring.count(ticket) || preparing.count(ticket) ||
+        preempting.count(ticket))
+        return true;
     for (auto *dq : {&incoming, &queue})
         for (auto &q : *dq)
             if (q->ticket == ticket) return true;
@@ -417,6 +593,7 @@ int da_submit(da_server *srv, const da_job *job, uint64_t *ticket) {
     if (j->footprint > (int64_t)srv->budget)
         return fail(nullptr, DA_ENOMEM, "job alone exceeds the server's device budget");
     j->spec = *job;
+    j->priority = job->priority;
     j->Q.assign(job->Q, job->Q + (size_t)job->N * job->N);
     j->spec.Q = j->Q.data();
     {
@@ -458,6 +635,35 @@ static int collect(da_server *srv, uint64_t ticket, da_result *out, da_job_stats
         if (out->final_E) std::memcpy(out->final_E, j->final_E.data(), j->final_E.size() * 8);
         if (out->n_accept) std::memcpy(out->n_accept, j->n_accept.data(), j->n_accept.size() * 8);
     }
+    return DA_OK;
+}
+
+int da_job_status(da_server *srv, uint64_t ticket, int32_t *state, int64_t *done_steps) {
+    if (!srv) return fail(nullptr, DA_EINVAL, "server is null");
+    std::lock_guard<std::mutex> lock(srv->mu);
+    int32_t st = -1;
+    int64_t done = 0;
+    auto f = srv->finished.find(ticket);
+    if (f != srv->finished.end()) {
+        st = 2;
+        done = f->second->done_steps;
+    } else if (srv->retiring.count(ticket)) {
+        st = 2;
+    } else {
+        for (auto &q : srv->resident)
+            if (q->ticket == ticket) {
+                st = 1;
+                done = q->done_steps;
+            }
+        if (st < 0 && srv->known_locked(ticket)) {
+            st = 0;
+            for (auto &q : srv->queue)
+                if (q->ticket == ticket) done = q->done_steps;
+        }
+    }
+    if (st < 0) return fail(nullptr, DA_ENOTFOUND, "unknown or already collected ticket");
+    if (state) *state = st;
+    if (done_steps) *done_steps = done;
     return DA_OK;
 }
 

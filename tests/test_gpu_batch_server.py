@@ -208,3 +208,65 @@ def test_server_poll_not_ready(api):
         assert time.time() - t0 < 120
         time.sleep(0.01)
     srv.close()
+
+
+def test_server_preemption(api):
+    """A high-priority job that does not fit preempts a running low-priority
+    one: the low job is snapshotted to host memory between epochs, released,
+    re-admitted after the high job, and resumes from its snapshot.  Both
+    results equal the jobs run alone, and a sampled replica of the preempted
+    job equals the oracle's."""
+    low = ("sk", 512, 16, 200_000, "zeros", 0, 64)
+    high = ("gauss", 384, 12, 3000, "random", 0, 32)
+    jobs, want, foot = [], [], []
+    for a, (kind, N, R, S, init, hint, L) in enumerate((low, high)):
+        Q, t = _job(kind, N, 120 + a)
+        sch = api.schedule(t["T_hi"], t["T_lo"], "geometric", L, t["eoff_inc"], init)
+        ctx = api.da_create(Q, hint)
+        want.append(api.da_anneal(ctx, sch, R, S, 60 + a))
+        foot.append(api.da_job_footprint(N, ctx.info()["dtype"], R, L))
+        ctx.close()
+        jobs.append((Q, sch, R, S, 60 + a, hint))
+    srv = api.da_server_create(max(foot) + min(foot) // 2, epoch_steps=500)
+    t_low = api.da_submit(srv, *jobs[0], priority=0)
+    t0 = time.time()
+    while True:   # wait until the low job is resident and has run an epoch
+        state, done = api.da_job_status(srv, t_low)
+        assert state != 2, "low-priority job finished before the high one arrived"
+        if state == 1 and done > 0:
+            break
+        assert time.time() - t0 < 60
+        time.sleep(0.001)
+    t_high = api.da_submit(srv, *jobs[1], priority=5)
+    r_high = api.da_wait(srv, t_high)
+    r_low = api.da_wait(srv, t_low)
+    with pytest.raises(api.DaError) as e:   # collected tickets are gone
+        api.da_job_status(srv, t_low)
+    assert e.value.code == api.DA_ENOTFOUND
+    srv.close()
+    for k in KEYS:
+        assert np.array_equal(r_high[k], want[1][k]), k
+        assert np.array_equal(r_low[k], want[0][k]), k
+    assert r_low["stats"]["preemptions"] >= 1
+    assert r_high["stats"]["preemptions"] == 0
+    assert r_low["stats"]["t_done"] > r_high["stats"]["t_done"]
+    kind, N, R, S, init, hint, L = low
+    _oracle_replica(kind, N, 120, 5, S, init, L, 60, r_low)
+
+
+def test_server_priority_order_without_preemption(api):
+    """A budget for one job at a time: waiting jobs are admitted by priority,
+    then submission order, and a waiting job whose priority is not above the
+    running job's preempts nothing."""
+    Q, t = _job("sk", 256, 9)
+    sch = api.schedule(t["T_hi"], t["T_lo"], "geometric", 16, 1)
+    fp = api.da_job_footprint(256, 1, 32, 16)
+    srv = api.da_server_create(fp + fp // 2, epoch_steps=400)
+    t1 = api.da_submit(srv, Q, sch, 32, 6000, 1, priority=1)
+    t2 = api.da_submit(srv, Q, sch, 32, 1000, 2, priority=0)
+    t3 = api.da_submit(srv, Q, sch, 32, 1000, 3, priority=1)
+    r = {k: api.da_wait(srv, k) for k in (t1, t2, t3)}
+    srv.close()
+    assert all(v["stats"]["preemptions"] == 0 for v in r.values())
+    assert r[t1]["stats"]["t_admit"] <= r[t3]["stats"]["t_admit"] <= r[t2]["stats"]["t_admit"]
+    assert r[t3]["stats"]["t_admit"] >= r[t1]["stats"]["t_done"] - 1e-6

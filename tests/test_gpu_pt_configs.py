@@ -192,3 +192,32 @@ def test_pt_full_size_sampled_chain(api):
     # every chain's slots are a permutation of the ladder
     for q in range(C):
         assert sorted(gpu["slot"][q * M:(q + 1) * M]) == list(range(M))
+
+
+@pytest.mark.parametrize("N,M,chains,iters,rounds,K", [
+    (64, 8, 4, 3, 20, 64), (300, 12, 3, 4, 10, 128), (1024, 16, 2, 2, 4, 1024),
+])
+def test_pt_adapt_parity(api, N, M, chains, iters, rounds, K):
+    """Adaptive ladder (Sec. II.D): PT runs on the device, per-pair acceptance
+    counts, ladder updates -- the final ladder and every iteration's measured
+    acceptances equal the oracle's."""
+    Q = instances.ising_to_qubo(instances.sk_bimodal(N, N + 1))[0]
+    temps = workloads.pt_temperatures(M, 0.1, 3.0, scale=N ** 0.5)
+    ctx = api.da_create(Q)
+    got, acc = api.da_pt_adapt(ctx, temps, chains, iters, rounds, K, 0, 3)
+    want, wacc = oracle.pt_adapt(Q, temps, chains=chains, iterations=iters, rounds=rounds,
+                                 steps_per_round=K, seed=3)
+    assert np.array_equal(got, want)
+    assert np.array_equal(acc, wacc)
+    assert got[0] == temps[0] and got[-1] == temps[-1]
+
+
+def test_pt_pair_swaps_parity(api):
+    N, M = 200, 9
+    Q = instances.ising_to_qubo(instances.sk_bimodal(N, 4))[0]
+    temps = workloads.pt_temperatures(M, 0.1, 3.0, scale=N ** 0.5)
+    ctx = api.da_create(Q)
+    gpu = api.da_pt(ctx, temps, 5, 70, 32, 1, 8)
+    ref = oracle.pt(Q, temps, chains=5, rounds=70, steps_per_round=32, eoff_inc=1, seed=8)
+    assert np.array_equal(gpu["pair_swaps"], ref["pair_swaps"])
+    assert np.array_equal(gpu["pair_swaps"].sum(axis=1), gpu["n_swaps"])

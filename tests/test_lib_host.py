@@ -74,3 +74,20 @@ def test_state_bytes(api):
     assert api.da_state_bytes(8192, 1) == 32 + 6 * 8192 + 28
     assert api.da_state_bytes(0, 1) == -1 and api.da_state_bytes(10, 0) == -1
     assert api.da_state_bytes(8193, 1) == -1
+
+
+def test_ladder_update_matches_oracle(api, orc):
+    """The adaptive-ladder update (Sec. II.D, Hukushima's scheme) decides the
+    temperatures of later PT runs, so the library's and the oracle's independent
+    writings of it must agree to the bit."""
+    g = np.random.Generator(np.random.PCG64(17))
+    for trial in range(300):
+        M = int(g.integers(1, 48))
+        temps = np.cumsum(g.uniform(0.01, 5.0, size=M)) + g.uniform(0.01, 1.0)
+        proposals = int(g.integers(0, 5000))
+        acc = g.integers(0, proposals + 1, size=max(M - 1, 1))
+        if trial % 7 == 0:
+            acc[:] = 0
+        got = api.da_pt_ladder_update(temps, acc[:max(M - 1, 0)] if M > 1 else acc, proposals)
+        want = orc.ladder_update(temps, acc, proposals)
+        assert np.array_equal(got, want), (M, proposals)
