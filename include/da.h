@@ -77,12 +77,12 @@ extern "C" {
 
 typedef struct da_ctx da_ctx;
 
-/* Temperature schedule of an anneal (Algorithm 2: "if due for temperature
- * update, update the temperature").  An S-step run is cut into n_levels equal
+/* Temperature schedule of an anneal (Algorithm 2 lowers the temperature at
+ * intervals during the run).  An S-step run is cut into n_levels equal
  * parts; step s uses level floor(s * n_levels / S).  T_hi and T_lo must be
  * > 0 for DA_SCHED_GEOMETRIC and DA_SCHED_LINEAR_BETA alike, except that
  * T_hi = T_lo = 0 selects a zero-temperature run (only strictly improving
- * flips, d < 0).  eoff_inc >= 0 is the offset_increase_rate of Algorithm 2
+ * flips, d < 0).  eoff_inc >= 0 is Algorithm 2's rate of offset increase
  * (0 switches the dynamic offset off, as in the paper's final runs, App. A).
  * 1 <= n_levels <= 4096, or n_levels = 0: a new temperature every step, as
  * in the paper's DA runs (App. A) -- step s runs at level s of an S-level

@@ -168,8 +168,9 @@ double orc_level_temperature(double T_hi, double T_lo, int kind, int L, int l)
     return T_hi * pow(T_lo / T_hi, frac);
 }
 
-/* Level in force at step s of an S-step run ("if due for temperature update,
- * update the temperature", Algorithm 2): the run is cut into L equal parts. */
+/* Level in force at step s of an S-step run (Algorithm 2 changes the
+ * temperature at intervals during the run): the run is cut into L equal
+ * parts. */
 int orc_level_of_step(int64_t s, int L, int64_t S)
 {
     if (S <= 0) return 0;

@@ -13,7 +13,8 @@ Also reported is 1 - (1 - P_s)^N, the value Eq. (2) would give if every
 variable were accepted with the mean single-flip probability independently.
 The instances are the synthetic stand-ins of `instances.py` (SK and 2D torus,
 +-1 and Gaussian couplings); temperatures are in Ising units of the
-unquantised couplings, and for +-1 SK in units of sqrt(N) (T_c = 1 for SK).  Run: python -m paper_1806_08815_amd.acceptance
+unquantised couplings, and for +-1 SK in units of sqrt(N) (T_c = 1 for SK).
+Run: python -m paper_1806_08815_amd.acceptance [temperature|size]
 """
 from __future__ import annotations
 
@@ -42,8 +43,10 @@ def acceptance(Q, T: float, trial: str, replicas: int, therm: int, meas: int, se
     return float((b - a).sum()) / (replicas * meas)
 
 
-def run(temps=None, replicas=512, therm_sweeps=500, meas_sweeps=200, seed=1) -> dict:
-    temps = list(np.geomspace(0.2, 3.0, 10)) if temps is None else temps
+def run(temps=None, replicas=256, therm_sweeps=100_000, meas_sweeps=5_000, seed=1) -> dict:
+    """P_s and P_p against T for the four N = 64 classes (Figs. 1-2), with the
+    paper's 10^5 thermalisation and 5 x 10^3 measured sweeps by default."""
+    temps = list(np.geomspace(0.2, 3.0, 8)) if temps is None else temps
     out = {}
     for name, make in CLASSES.items():
         J = make(seed)
@@ -65,7 +68,29 @@ def run(temps=None, replicas=512, therm_sweeps=500, meas_sweeps=200, seed=1) -> 
     return out
 
 
+def boost_vs_size(sizes=(64, 256, 1024), T=0.2, replicas=256, sweeps=None, seed=1) -> list:
+    """P_p / P_s against N at a low temperature on +-1 SK instances (T in units
+    of sqrt(N), T_c = 1): the parallel trial's advantage grows with N, and
+    P_p / P_s approaches N while N P_s << 1 (Eq. (2) expanded for small P_s).
+    Sweeps (thermalisation, measured) per size default to (10^5, 5 x 10^3) at
+    N = 64 and fewer at larger N, where a sweep costs N times more steps."""
+    sweeps = sweeps or {64: (100_000, 5_000), 256: (10_000, 2_000), 1024: (2_000, 500)}
+    rows = []
+    for N in sizes:
+        Q = instances.ising_to_qubo(instances.sk_bimodal(N, seed))[0]
+        th, me = sweeps[N]
+        Ta = T * N ** 0.5
+        ps = acceptance(Q, Ta, "single", replicas, th * N, me * N, seed)
+        pp = acceptance(Q, Ta, "parallel", replicas, th * N, me * N, seed)
+        rows.append({"N": N, "T": T, "therm_sweeps": th, "meas_sweeps": me, "P_s": ps,
+                     "P_p": pp, "ratio": pp / ps if ps > 0 else None,
+                     "ratio_over_N": (pp / ps / N) if ps > 0 else None,
+                     "independent_trials": 1.0 - (1.0 - ps) ** N})
+    return rows
+
+
 if __name__ == "__main__":
-    res = run()
+    which = sys.argv[1] if len(sys.argv) > 1 else "temperature"
+    res = run() if which == "temperature" else boost_vs_size()
     json.dump(res, sys.stdout, indent=1)
     print()

@@ -64,6 +64,34 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     return make_uint4(c0, c1, c2, c3);
 }
 
+// Word 0 of Philox4x32-10 for a counter and key that are the same in every
+// lane of the wave (the selection draw): written with 32-bit high and low
+// products of wave-uniform operands, so the ten rounds run on the scalar
+// unit instead of taking vector issue slots.  Same function as philox().x.
+__device__ __forceinline__ uint32_t philox_x_uniform(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                     uint32_t c3, uint32_t k0, uint32_t k1) {
+    c0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)c0);
+    c1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)c1);
+    c2 = (uint32_t)__builtin_amdgcn_readfirstlane((int)c2);
+    c3 = (uint32_t)__builtin_amdgcn_readfirstlane((int)c3);
+    k0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)k0);
+    k1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)k1);
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += kPhiloxW0;
+            k1 += kPhiloxW1;
+        }
+        const uint32_t hi0 = __umulhi(kPhiloxM0, c0), lo0 = kPhiloxM0 * c0;
+        const uint32_t hi1 = __umulhi(kPhiloxM1, c2), lo1 = kPhiloxM1 * c2;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+    }
+    return c0;
+}
+
 __device__ __forceinline__ uint32_t word_of(const uint4 &v, int w) {
     return w == 0 ? v.x : (w == 1 ? v.y : (w == 2 ? v.z : v.w));
 }
@@ -414,7 +442,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             draws[(int)(st & 1) * NH * 64 + b] =
                 philox((uint32_t)b, (uint32_t)st, rid, kTagMetropolis, k0, k1);
         if (active && wr == NH - 1) {
-            const uint32_t v = philox(0u, (uint32_t)st, rid, kTagSelect, k0, k1).x;
+            const uint32_t v = philox_x_uniform(0u, (uint32_t)st, rid, kTagSelect, k0, k1);
             if (lane == 0) vring[(int)(st & 3)] = v;
         }
     };
@@ -699,7 +727,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             m = wtot;
             if (m > 0) {
                 const uint32_t v = HELP ? (uint32_t)__builtin_amdgcn_readfirstlane((int)vs)
-                                        : philox(0u, (uint32_t)s, rid, kTagSelect, k0, k1).x;
+                                        : philox_x_uniform(0u, (uint32_t)s, rid, kTagSelect, k0, k1);
                 const int j = (int)(((uint64_t)v * (uint32_t)m) >> 32);
                 const uint64_t bal = ballot(excl + c > j);
                 const int ts = (int)__builtin_ctzll(bal);
@@ -728,7 +756,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             m = readlane(scan, NW - 1);
             if (m > 0) {
                 const uint32_t v = HELP ? (uint32_t)__builtin_amdgcn_readfirstlane((int)vs)
-                                        : philox(0u, (uint32_t)s, rid, kTagSelect, k0, k1).x;
+                                        : philox_x_uniform(0u, (uint32_t)s, rid, kTagSelect, k0, k1);
                 const int j = (int)(((uint64_t)v * (uint32_t)m) >> 32);
                 const uint64_t wbal = ballot(scan > j) & ((1ull << NW) - 1ull);
                 const int ws = (int)__builtin_ctzll(wbal);

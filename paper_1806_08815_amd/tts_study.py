@@ -1,0 +1,93 @@
+"""Time to solution against the anneal length (Sec. IV), measured on the GPU.
+
+The paper notes that TTS has a minimum in the number of sweeps: too short an
+anneal rarely reaches the optimum, too long a one wastes time on runs that
+would have succeeded sooner.  For a fully connected Gaussian SK instance (the
+class of the N = 1024 Gaussian workload; J ~ N(0,1)/sqrt(N) at fixed point
+2^16) this runs R replicas of the DA at each anneal length S (geometric
+T 3.0 -> 0.05, offset increment 1 in units of the couplings), counts the runs
+reaching a reference energy E_ref, and reports
+
+    theta = Jeffreys posterior median of the success probability,
+    R99   = log(0.01) / log(1 - theta),
+    TTS99 = t(R99), the wall time of one launch of ceil(R99) replicas,
+
+with t(R99) timed directly when ceil(R99) <= R and otherwise the time of the
+R-replica launch scaled by R99 / R (the GPU is full at R replicas, so more
+runs cost proportionally more time).  E_ref is the best energy of an
+independent parallel-tempering run on the same instance (an upper bound on
+the optimum), so the runs it scores never set it.
+
+Run: python -m paper_1806_08815_amd.tts_study [N]
+"""
+from __future__ import annotations
+
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import api, instances, tts, workloads
+
+
+def reference_energy(Q, N, chains=64, M=32, rounds=2000, K=None, seed=77):
+    temps = workloads.pt_temperatures(M, 0.1, 3.0, float(workloads.GAUSS_SCALE))
+    ctx = api.da_create(Q)
+    o = api.da_pt(ctx, temps, chains, rounds, K or N, 0, seed)
+    ctx.close()
+    return int(o["best_E"].min())
+
+
+def tts_curve(N=256, instance_seed=3, replicas=1024, steps_list=None, seed=1, E_ref=None):
+    import torch
+    steps_list = steps_list or [1_000, 3_000, 10_000, 30_000, 100_000, 300_000, 1_000_000]
+    J = instances.sk_gaussian(N, instance_seed, scale=workloads.GAUSS_SCALE)
+    Q, const = instances.ising_to_qubo(J)
+    t0 = time.perf_counter()
+    if E_ref is None:
+        E_ref = reference_energy(Q, N)
+    t_ref = time.perf_counter() - t0
+    ctx = api.da_create(Q)
+    sc = float(workloads.GAUSS_SCALE)
+    stream = torch.cuda.current_stream()
+    rows = []
+    for S in steps_list:
+        sch = api.schedule(3.0 * sc, 0.05 * sc, "geometric", 128, int(sc))
+        out = api.device_outputs(replicas, N)
+        api.da_anneal_async(ctx, sch, 0, replicas, S, seed, None, out, stream)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        api.da_anneal_async(ctx, sch, 0, replicas, S, seed, None, out, stream)
+        torch.cuda.synchronize()
+        t_R = time.perf_counter() - t
+        best = out["best_E"].cpu().numpy()
+        y = tts.success_count(best, E_ref)
+
+        def time_launch(reps):
+            if reps > replicas:
+                return t_R * reps / replicas
+            o = api.device_outputs(reps, N)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            api.da_anneal_async(ctx, sch, 0, reps, S, seed, None, o, stream)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t1
+
+        r = tts.tts99_measured(y, replicas, time_launch)
+        rows.append({"steps": S, "sweeps": S / N, "successes": y, "runs": replicas,
+                     "theta_median": r["theta"], "r99": r["r99"],
+                     "tts99_s": r["tts_s"], "launch_s": t_R,
+                     "best_minus_ref": int(best.min()) - E_ref})
+    finite = [r for r in rows if math.isfinite(r["tts99_s"])]
+    best_row = min(finite, key=lambda r: r["tts99_s"]) if finite else None
+    return {"N": N, "class": "sk-gaussian", "instance_seed": instance_seed,
+            "E_ref": E_ref + int(const), "E_ref_seconds": t_ref, "replicas": replicas,
+            "curve": rows, "optimal_steps": best_row["steps"] if best_row else None}
+
+
+if __name__ == "__main__":
+    N = int(sys.argv[1]) if len(sys.argv) > 1 else 256
+    json.dump(tts_curve(N), sys.stdout, indent=1)
+    print()
