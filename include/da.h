@@ -348,6 +348,24 @@ int da_pt_adapt(da_ctx *ctx, double *temps, int32_t M, int32_t chains, int32_t i
  * DA_EDEVICE. */
 int da_energy(da_ctx *ctx, const uint8_t *x, int32_t count, int64_t *E);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): da_energy
+ * on device buffers, with no allocation.  x_dev [count][N] uint8 (nonzero =
+ * 1) and E_dev [count] int64 are device buffers owned by the caller; the work
+ * is enqueued on `stream` (a hipStream_t; NULL = the null stream) and the
+ * call returns without waiting.  The intermediates (padded states, local
+ * fields) live in a fixed 32 MiB scratch array the library holds on each
+ * device until the process ends, so count is limited by
+ *   ceil(count * ld / 256) * 256 + 4 * count * ld <= 2^25,  ld = N rounded up to 64
+ * (6553 states at N = 1024, 819 at N = 8192); a larger count is rejected
+ * with DA_EINVAL before any work.  Every call on a device shares that
+ * device's scratch and the last call's contents stay there: calls that
+ * overlap on one GPU (other streams, threads or contexts) race, and the
+ * caller must order them.  Errors: DA_EINVAL (nulls, count < 1 or too large,
+ * context on another device), DA_EDEVICE. */
+int da_energy_noalloc(da_ctx *ctx, const uint8_t *x_dev, int32_t count, int64_t *E_dev,
+                      void *stream);
+
 /* Stats of the context's step kernels (synchronises with the last end event;
  * call it outside timed regions). */
 int da_last_kernel_stats(da_ctx *ctx, da_kernel_stats *stats);

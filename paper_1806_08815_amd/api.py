@@ -128,6 +128,7 @@ def lib() -> ctypes.CDLL:
         "da_pt": (_i32, [_P, _P, _i32, _i32, _i64, _i32, _i32, _u64,
                          ctypes.POINTER(da_pt_result)]),
         "da_energy": (_i32, [_P, _P, _i32, _P]),
+        "da_energy_noalloc": (_i32, [_P, _P, _i32, _P, _P]),
         "da_pt_ladder_update": (_i32, [_i32, _P, _P, _i64, _P]),
         "da_pt_adapt": (_i32, [_P, _P, _i32, _i32, _i32, _i64, _i32, _i32, _u64, _P]),
         "da_last_kernel_stats": (_i32, [_P, ctypes.POINTER(da_kernel_stats)]),
@@ -390,6 +391,16 @@ def da_energy(ctx: Ctx, x) -> np.ndarray:
     E = np.zeros(x.shape[0], np.int64)
     _check(lib().da_energy(ctx.ptr, _ptr(x), x.shape[0], _ptr(E)), ctx.ptr)
     return E
+
+
+def da_energy_noalloc(ctx: Ctx, x_dev, E_dev, stream=None) -> None:
+    """Energies of the device states x_dev [count][N] (torch uint8) into E_dev
+    [count] (torch int64), enqueued on `stream`; allocates nothing."""
+    count = int(x_dev.shape[0])
+    assert x_dev.dtype.itemsize == 1 and x_dev.is_contiguous() and x_dev.shape[1] == ctx.N
+    assert E_dev.dtype.itemsize == 8 and E_dev.is_contiguous() and E_dev.shape[0] >= count
+    _check(lib().da_energy_noalloc(ctx.ptr, x_dev.data_ptr(), count, E_dev.data_ptr(),
+                                   _stream_ptr(stream)), ctx.ptr)
 
 
 def da_last_kernel_stats(ctx: Ctx) -> dict:

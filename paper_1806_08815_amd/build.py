@@ -19,7 +19,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdapt.so")
-SOURCES = ["da_kernels.hip", "da_probe.hip", "da_tables.cpp", "da_api.cpp", "da_server.cpp"]
+SOURCES = ["da_kernels.hip", "da_probe.hip", "da_tables.cpp", "da_api.cpp", "da_server.cpp",
+           "da_noalloc.hip"]
 HEADERS = ["da_internal.h", "da_runtime.h"]
 
 
