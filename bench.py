@@ -441,8 +441,14 @@ def serve_bench(api, workloads, n_jobs: int, seed: int, budget_gb: float, epoch_
         ctx.close()
         return time.perf_counter() - t, o
 
-    for j, Q, sch in zip(jobs, Qs, scheds):   # launch-shape tuner, untimed
-        plain(j, Q, sch, min(j["steps"], 1000))
+    # the launch-shape tuner runs once per (N, coupling type, replica-count
+    # bucket): let it run here, untimed, for every combination in the stream
+    seen = set()
+    for j, Q, sch in zip(jobs, Qs, scheds):
+        key = (j["N"], j["kind"], 1 << (int(j["replicas"]) - 1).bit_length())
+        if key not in seen:
+            seen.add(key)
+            plain(j, Q, sch, min(j["steps"], 1000))
     torch.cuda.synchronize()
     service, alone = [], []
     for j, Q, sch in zip(jobs, Qs, scheds):

@@ -17,6 +17,7 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+import threading
 
 import numpy as np
 
@@ -43,11 +44,16 @@ def build(force: bool = True) -> str:
 
 
 _lib = None
+_lib_lock = threading.Lock()
 
 
 def lib() -> ctypes.CDLL:
     global _lib
-    if _lib is None:
+    if _lib is not None:
+        return _lib
+    with _lib_lock:   # callers on several threads build and bind it once
+        if _lib is not None:
+            return _lib
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build()
         L = ctypes.CDLL(_LIB)
