@@ -121,7 +121,7 @@ int validate_schedule(const da_schedule *s, std::string &err) {
 LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch,
                          bool anneal_mode, bool direct) {
     LaunchShape sh;
-    const int stage = anneal_mode ? 1 : 0;
+    int stage = anneal_mode ? 1 : 0;
     const int cus = ctx->cus;
     // Few replicas per CU: each replica's step latency is the limit, so spread
     // a replica over more waves (4 variables per lane) and move the random
@@ -145,6 +145,9 @@ LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch,
     rpw = std::max(1, std::min(rpw, 16 / per));
     rpw = std::min(rpw, std::max(R, 1));
     sh.RPW = rpw;
+    // parallel tempering with one replica per workgroup stages the level of
+    // that replica for each round (the launcher picks that variant)
+    if (!anneal_mode && rpw == 1) stage = 1;
     // what an anneal may stage in LDS: the sparse lists, else dense W
     const int64_t w_bytes = (anneal_mode && ctx->ell_D > 0)
                                 ? (int64_t)ctx->N * ctx->ell_D * 4

@@ -378,7 +378,10 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     // --- level in force ----------------------------------------------------
     int lvl;
     int64_t s_next;
-    if (!stage) {
+    if (J.lvl_of_rep) {
+        // parallel tempering: one level per replica for the whole launch (a
+        // round); with STAGE the workgroup holds one replica and stages its
+        // level's brackets
         lvl = active ? J.lvl_of_rep[rr] : 0;
         s_next = INT64_MAX;
     } else {
@@ -1306,6 +1309,20 @@ int launch_run_t(const JobDesc &J, const TraceDesc &T, int blocks, int threads, 
     const bool wide = J.NW > 1 && !J.w_lds &&
                       (sizeof(WT) != 2 || (J.wscale < (1 << 15) && J.wscale > -(1 << 15)));
     if (J.lvl_of_rep) {
+        // one replica per workgroup: its level's brackets are staged in LDS
+        // for the round; several replicas (possibly at different levels) read
+        // theirs through L1/L2
+        if constexpr (!TRACE) {
+            if (J.RPW == 1) {
+                if (wide)
+                    hipLaunchKernelGGL((k_run<WT, F, false, HELP, true, kModeWide>), g, b, lds,
+                                       S(stream), J, T);
+                else
+                    hipLaunchKernelGGL((k_run<WT, F, false, HELP, true, kModePlain>), g, b, lds,
+                                       S(stream), J, T);
+                return (int)hipGetLastError();
+            }
+        }
         if (wide)
             hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, false, kModeWide>), g, b, lds,
                                S(stream), J, T);
