@@ -299,13 +299,22 @@ def pt_leg(api, workloads, rounds: int):
     fe = R * steps * p["N"]
     acc = float(out["n_accept"].sum()) / (R * steps)
     pair = out["pair_swaps"].sum(axis=0) / (p["chains"] * rounds)
+    dtype = ctx.info()["dtype"]
+    stream_gbps = acc * R * steps * p["N"] * dtype / (ks["kernel_ms"] / 1e3) / 1e9
+    # the same gather at the same chain count: rows of N * dtype bytes (int8 rows
+    # are probed as int16 rows of half the elements, the same bytes)
+    elems = p["N"] * dtype // 2
+    probe = api.da_probe_row_stream(p["N"], elems, 2, R, max(1, -(-p["N"] // 512)), 20_000)
     return {
         "workload": f"{p['name']}: {p['kind']} N={p['N']}, {p['chains']} chains x M={p['M']} "
                     f"temperatures, K={p['steps_per_round']} steps per round, random start",
         "rounds": rounds, "rounds_full": p["rounds"], "seconds": dt,
         "flip_evals_per_s": fe / dt, "ns_per_round_step": ks["kernel_ms"] / steps * 1e6,
         "accepted_step_fraction": acc,
-        "row_stream_GBps": acc * R * steps * p["N"] * ctx.info()["dtype"] / (ks["kernel_ms"] / 1e3) / 1e9,
+        "row_stream_GBps": stream_gbps,
+        "row_stream_achievable_GBps": probe["GBps"],
+        "row_stream_frac": stream_gbps / probe["GBps"],
+        "hbm_frac": stream_gbps / HBM_PEAK_GBS,
         "exchange_decisions": int(rounds * p["chains"] * (p["M"] - 1)),
         "swaps_accepted": int(np.asarray(out["n_swaps"]).sum()),
         "pair_acceptance_min_max": [float(pair.min()), float(pair.max())],

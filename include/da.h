@@ -126,7 +126,8 @@ typedef struct da_trace {
 
 /* Launch-shape knobs; zero fields mean "choose automatically" (autotuned
  * table).  Results never depend on them.
- *   flips_per_lane      4 or 8 variables per GPU lane
+ *   flips_per_lane      2, 4 or 8 variables per GPU lane (2: 8/16-bit
+ *                       couplings only, else 4)
  *   replicas_per_block  replicas sharing one workgroup (1..16)
  *   w_in_lds            1: stage W in LDS when it fits; -1: never; 0: auto
  *   rng_waves           1: dedicated random-number waves generate each

@@ -131,7 +131,8 @@ LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch,
     const int want_help = launch ? launch->rng_waves : 0;
     bool help = want_help > 0 || (want_help == 0 && latency_bound);
     sh.F = (launch && launch->flips_per_lane) ? launch->flips_per_lane : (latency_bound ? 4 : 8);
-    if (sh.F != 4 && sh.F != 8) sh.F = 8;
+    if (sh.F != 2 && sh.F != 4 && sh.F != 8) sh.F = 8;
+    if (sh.F == 2 && ctx->dtype > 2) sh.F = 4;   // two per lane: 8/16-bit couplings only
     sh.NW = (ctx->N + 64 * sh.F - 1) / (64 * sh.F);
     if (sh.NW > 16) {  // keep a replica within one workgroup (N <= 8192)
         sh.F = 8;
@@ -600,7 +601,8 @@ int tuned_shape(da_ctx *ctx, const LevelTables &lt, int32_t R, int64_t steps,
     // W staged in LDS is a candidate whenever it fits there
     const bool w_fits = ctx->ell_D == 0 &&
                         (int64_t)ctx->N * ctx->ld * ctx->dtype <= (int64_t)device_lds_limit();
-    for (int F : {4, 8}) {
+    for (int F : {2, 4, 8}) {
+        if (F == 2 && ctx->dtype > 2) continue;
         for (int rpw : {1, 2, 4}) {
             for (int rng : {1, -1})
             for (int wl : {-1, 1}) {

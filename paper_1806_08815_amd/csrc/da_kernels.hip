@@ -149,7 +149,8 @@ __device__ __forceinline__ int select_bit4(uint32_t m, int r) {
 // (table lookups, no loop over bits).
 template <int F>
 __device__ __forceinline__ int select_bit(uint32_t m, int r) {
-    static_assert(F == 4 || F == 8, "4 or 8 flips per lane");
+    static_assert(F == 2 || F == 4 || F == 8, "2, 4 or 8 flips per lane");
+    if (F == 2) return (r == 0 && (m & 1u)) ? 0 : 1;
     if (F == 4) return select_bit4(m, r);
     const uint32_t low = m & 15u;
     const int c = __popc(low);
@@ -181,7 +182,11 @@ __device__ __forceinline__ void load_row(const WT *p, int (&w)[F]) {
 template <typename WT, int F>
 __device__ __forceinline__ void update_i16(const typename VecOf<WT, F>::type &raw, int dw,
                                            int (&h)[F]) {
-    if constexpr (sizeof(WT) == 2) {
+    if constexpr (sizeof(WT) == 2 && F == 2) {
+        const int pr = __builtin_bit_cast(int, raw);
+        asm("v_mad_i32_i16 %0, %1, %2, %0" : "+v"(h[0]) : "v"(pr), "s"(dw));
+        asm("v_mad_i32_i16 %0, %1, %2, %0 op_sel:[1,0,0,0]" : "+v"(h[1]) : "v"(pr), "s"(dw));
+    } else if constexpr (sizeof(WT) == 2) {
         typedef typename VecOf<int, F / 2>::type PairV;
         const PairV pr = __builtin_bit_cast(PairV, raw);
 #pragma unroll
@@ -262,7 +267,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     const bool single = MODE == kModeDynamic ? J.single != 0 : (MODE & kModeSingle) != 0;
     const bool perstep = MODE == kModeDynamic ? J.stepT != nullptr : (MODE & kModePerStep) != 0;
     const bool sparse = MODE == kModeDynamic ? J.ell != nullptr : (MODE & kModeSparse) != 0;
-    static_assert(F == 4 || F == 8, "a lane's record holds at most 8 flips");
+    static_assert(F == 2 || F == 4 || F == 8, "a lane's record holds at most 8 flips");
     constexpr int NB = (F + 7) / 8;   // Philox blocks per lane
     typedef typename VecOf<WT, F>::type RowV;
     const int lane = threadIdx.x & 63;
@@ -456,10 +461,14 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         if (F >= 8) {
 #pragma unroll
             for (int q = 0; q < NB; ++q) dst[q] = src[min((i0 >> 3) + q, NH * 64 - 1)];
-        } else {
+        } else if (F == 4) {
             const uint2 *s2 = reinterpret_cast<const uint2 *>(src);
             const uint2 p = s2[min(i0 >> 2, 2 * NH * 64 - 1)];   // half of block i0 >> 3
             dst[0] = make_uint4(p.x, p.y, p.x, p.y);
+        } else {
+            const uint32_t *s1 = reinterpret_cast<const uint32_t *>(src);
+            const uint32_t w = s1[min(i0 >> 1, 4 * NH * 64 - 1)];   // word of block i0 >> 3
+            dst[0] = make_uint4(w, w, w, w);
         }
     };
 
@@ -1396,6 +1405,13 @@ template <typename WT, bool TRACE, bool HELP>
 int launch_run_f(const JobDesc &J, int F, const TraceDesc &T, int blocks, int threads, size_t lds,
                  void *stream) {
     switch (F) {
+        case 2:
+            // two flips per lane: 8- and 16-bit couplings (replicas spread over
+            // twice the waves when the chip has room for them)
+            if constexpr (sizeof(WT) <= 2)
+                return launch_run_t<WT, 2, TRACE, HELP>(J, T, blocks, threads, lds, stream);
+            else
+                return (int)hipErrorInvalidValue;
         case 4: return launch_run_t<WT, 4, TRACE, HELP>(J, T, blocks, threads, lds, stream);
         case 8: return launch_run_t<WT, 8, TRACE, HELP>(J, T, blocks, threads, lds, stream);
         default: return (int)hipErrorInvalidValue;

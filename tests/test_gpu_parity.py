@@ -377,3 +377,48 @@ def test_snapshot_offset_out_of_range_rejected(api):
         api.da_state_load(ctx, bad)
     assert e.value.code == api.DA_EINVAL
     api.da_state_load(ctx, snap)
+
+
+@pytest.mark.parametrize("rng", [1, -1])
+@pytest.mark.parametrize("kind,N,dtype,L,S,extra", [
+    ("sk", 1024, 2, 16, 700, {}), ("sk", 1000, 0, 4, 1600, {}),       # narrow bands, direct tables
+    ("gauss", 1024, 0, 16, 700, {}), ("random", 257, 2, 16, 700, {}),  # wide bands, ragged N
+    ("sk", 2000, 0, 8, 400, {}),                                       # 16 compute waves
+    ("random", 200, 2, 16, 700, {"w_lds": 1}),                         # W in LDS
+    ("sk", 300, 0, 16, 637, {"trial": "single"}),                      # single trial
+    ("sk", 500, 2, 0, 600, {}),                                        # a new temperature every step
+])
+def test_two_flips_per_lane_trace_parity(api, kind, N, dtype, L, S, extra, rng):
+    """Two variables per lane (8- and 16-bit couplings): twice the compute waves
+    of four per lane, selection over up to 16 waves."""
+    Q = _q(kind, N, 33)
+    if kind == "gauss":
+        T_hi, T_lo, inc = 3.0 * 2**16, 0.05 * 2**16, 2**16
+    elif kind == "random":
+        T_hi, T_lo, inc = 4000.0, 10.0, 50
+    else:
+        T_hi, T_lo, inc = 3.0 * N ** 0.5, 0.1, 1
+    trial = extra.get("trial", "parallel")
+    if trial == "single":
+        inc = 0
+    R = 4
+    ctx = api.da_create(Q, dtype)
+    sch = api.schedule(T_hi, T_lo, "geometric", L, eoff_inc=inc, trial=trial)
+    gpu = api.da_anneal_ex(ctx, sch, 2, R, S, 41, api.launch(2, 1, extra.get("w_lds", 0), rng),
+                           trace=True)
+    assert api.da_last_kernel_stats(ctx)["flips_per_lane"] == 2
+    ref = oracle.anneal(Q, T_hi=T_hi, T_lo=T_lo, n_levels=L, eoff_inc=inc, replica_base=2,
+                        replicas=R, steps=S, seed=41, trace=True,
+                        trial=1 if trial == "single" else 0)
+    _same(gpu, ref, ("trace_k", "trace_E", "trace_eoff") + KEYS)
+
+
+def test_two_flips_per_lane_falls_back_for_int32(api):
+    Q = _q("gauss", 300, 3)
+    ctx = api.da_create(Q, 4)
+    sch = api.schedule(3.0 * 2**16, 0.05 * 2**16, "geometric", 8, eoff_inc=2**16)
+    gpu = api.da_anneal_ex(ctx, sch, 0, 3, 500, 2, api.launch(2, 1, 0, 1))
+    assert api.da_last_kernel_stats(ctx)["flips_per_lane"] == 4
+    ref = oracle.anneal(Q, T_hi=3.0 * 2**16, T_lo=0.05 * 2**16, n_levels=8, eoff_inc=2**16,
+                        replicas=3, steps=500, seed=2)
+    _same(gpu, ref)
