@@ -175,7 +175,8 @@ def small_sk_leg(api, oracle, workloads):
         "wall_ms_per_anneal": wall * 1e3,
         "flip_evals_per_s": w.replicas * w.steps * w.N / wall,
         "launch": {k: ks[k] for k in ("blocks", "threads", "flips_per_lane",
-                                      "replicas_per_block", "w_in_lds", "rng_waves")},
+                                      "replicas_per_block", "w_in_lds", "rng_waves",
+                                      "draw_estimates")},
         "oracle_all_replicas_equal": same_rows(gpu, ref),
         "oracle_single_core_flip_evals_per_s": w.steps * w.N / (sum(per) / len(per)),
     }
@@ -533,8 +534,9 @@ def main() -> int:
     ap.add_argument("--workload", default="sk-gaussian-1024")
     ap.add_argument("--dtype", type=int, default=None, help="force coupling storage bytes")
     ap.add_argument("--launch", default=None,
-                    help="fixed step-kernel shape F:RPW:RNG (flips per lane, replicas per "
-                         "workgroup, random-number waves: 1 on, -1 off) instead of the tuned one")
+                    help="fixed step-kernel shape F:RPW:RNG[:EST] (flips per lane, replicas per "
+                         "workgroup, random-number waves: 1 on, -1 off, per-draw estimates: 1 "
+                         "on, -1 off) instead of the tuned one")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-extras", action="store_true")
     ap.add_argument("--legs", default="small,torus,tts,pt,ladder,serve,checkpoint,perstep,mfma,sparse",
@@ -572,8 +574,10 @@ def main() -> int:
 
     fixed = None
     if args.launch:
-        F_, rpw_, rng_ = (int(v) for v in args.launch.split(":"))
-        fixed = api.launch(F_, rpw_, 0, rng_)
+        parts = [int(v) for v in args.launch.split(":")]
+        F_, rpw_, rng_ = parts[:3]
+        est_ = parts[3] if len(parts) > 3 else 0
+        fixed = api.launch(F_, rpw_, 0, rng_, est_)
 
     def anneal():
         api.da_anneal_async(ctx, sch, 0, R, S, w.seed, fixed, out, stream)
@@ -602,7 +606,7 @@ def main() -> int:
     # the achievable rate of the same access pattern at the same chain count
     peak = row_stream_peak(api, N, info["dtype"], R) if info["dtype"] in (2, 4) else None
     launch = {k: ks[k] for k in ("blocks", "threads", "flips_per_lane", "replicas_per_block",
-                                 "w_in_lds", "rng_waves")}
+                                 "w_in_lds", "rng_waves", "draw_estimates")}
     traffic = measured_traffic(args.workload, launch)
     ns_step = kernel_s / S * 1e9
     result = {

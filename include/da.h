@@ -133,12 +133,19 @@ typedef struct da_trace {
  *   rng_waves           1: dedicated random-number waves generate each
  *                       step's draws one step ahead, off the critical path;
  *                       -1: the compute waves draw lazily, only for undecided
- *                       flips; 0: auto */
+ *                       flips; 0: auto
+ *   draw_estimates      with random-number waves, wide bands and at least 4
+ *                       flips per lane: 1 lets those waves also hand over an
+ *                       fp32 estimate of each draw's threshold, so most flips
+ *                       are decided by one compare and only flips inside the
+ *                       estimate's measured window read the exact table;
+ *                       -1: never; 0: auto */
 typedef struct da_launch {
     int32_t flips_per_lane;
     int32_t replicas_per_block;
     int32_t w_in_lds;
     int32_t rng_waves;
+    int32_t draw_estimates;
 } da_launch;
 
 /* What the step-kernel launches of a context looked like and how long they
@@ -155,7 +162,7 @@ typedef struct da_kernel_stats {
     int32_t w_in_lds;
     int32_t rng_waves;         /* random-number waves per replica (0: lazy)  */
     int32_t dtype;             /* bytes per stored coupling                  */
-    int32_t reserved;
+    int32_t draw_estimates;    /* 1: the step kernel took per-draw estimates */
 } da_kernel_stats;
 
 /* Static facts about a context. */

@@ -49,14 +49,14 @@ class da_trace(ctypes.Structure):
 
 class da_launch(ctypes.Structure):
     _fields_ = [("flips_per_lane", _i32), ("replicas_per_block", _i32), ("w_in_lds", _i32),
-                ("rng_waves", _i32)]
+                ("rng_waves", _i32), ("draw_estimates", _i32)]
 
 
 class da_kernel_stats(ctypes.Structure):
     _fields_ = [("kernel_ms", _dbl), ("total_ms", _dbl), ("launches", _i64), ("blocks", _i32),
                 ("threads", _i32),
                 ("flips_per_lane", _i32), ("replicas_per_block", _i32), ("w_in_lds", _i32),
-                ("rng_waves", _i32), ("dtype", _i32), ("reserved", _i32)]
+                ("rng_waves", _i32), ("dtype", _i32), ("draw_estimates", _i32)]
 
 
 class da_info(ctypes.Structure):
@@ -187,8 +187,9 @@ def schedule(T_hi: float, T_lo: float, kind: str | int = "geometric", n_levels: 
 
 
 def launch(flips_per_lane: int = 0, replicas_per_block: int = 0, w_in_lds: int = 0,
-           rng_waves: int = 0) -> da_launch:
-    return da_launch(int(flips_per_lane), int(replicas_per_block), int(w_in_lds), int(rng_waves))
+           rng_waves: int = 0, draw_estimates: int = 0) -> da_launch:
+    return da_launch(int(flips_per_lane), int(replicas_per_block), int(w_in_lds), int(rng_waves),
+                     int(draw_estimates))
 
 
 class Ctx:

@@ -176,6 +176,19 @@ LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch,
         sh.direct = 0;
         sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0, stage, sh.NH, sparse);
     }
+    // per-draw estimates: random-number waves, a multi-wave replica reading W
+    // from global memory (the wide variants), 4 or 8 flips per lane, and fields
+    // small enough for the estimate path's int32 sums; not with direct tables
+    const int want_gen = launch ? launch->draw_estimates : 0;
+    const bool wide16 = ctx->dtype != 2 || (ctx->wscale < (1 << 15) && ctx->wscale > -(1 << 15));
+    if (want_gen >= 0 && anneal_mode && !sparse && !sh.direct && !sh.w_lds && sh.NH > 0 &&
+        sh.NW > 1 && sh.F >= 4 && wide16 && ctx->hbound <= kGenFieldMax) {
+        const size_t lg = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0, stage, sh.NH, false, false, true);
+        if (lg <= limit) {
+            sh.gen = 1;
+            sh.lds = lg;
+        }
+    }
     return sh;
 }
 
@@ -218,6 +231,7 @@ JobDesc make_job(const da_ctx *ctx, const LevelTables &lt, int32_t R, uint32_t r
     J.brk = lt.d_brk;
     J.thr = lt.d_thr;
     J.q8 = sh.direct ? lt.d_q8 : nullptr;
+    J.gth = (sh.gen && lt.any_gth && s.trial != DA_TRIAL_SINGLE) ? 1 : 0;
     return J;
 }
 
@@ -441,12 +455,16 @@ int derive_storage(const int32_t *Q, int32_t N, int32_t dtype_hint, int32_t &dty
 
 namespace {
 template <typename T>
-void fill_padded(const int32_t *Q, size_t n, size_t ld, int64_t g, uint8_t *dst) {
+void fill_padded(const int32_t *Q, size_t n, size_t ld, int64_t g, uint8_t *dst,
+                 std::vector<int64_t> &row) {
     T *W = reinterpret_cast<T *>(dst);
     for_upper_pairs(Q, n, [&](size_t i, size_t j, int64_t w) {
         const T v = (T)(w / g);
         W[i * ld + j] = v;
         W[j * ld + i] = v;
+        const int64_t aw = w < 0 ? -w : w;
+        row[i] += aw;
+        row[j] += aw;
     });
 }
 }  // namespace
@@ -458,11 +476,16 @@ void prepare_matrix(const int32_t *Q, int32_t N, int32_t dtype, int32_t wscale, 
     hm.wscale = wscale;
     const size_t n = (size_t)N, ld = (size_t)hm.ld;
     hm.W.assign(ld * ld * (size_t)dtype, 0);
-    if (dtype == 1) fill_padded<int8_t>(Q, n, ld, wscale, hm.W.data());
-    else if (dtype == 2) fill_padded<int16_t>(Q, n, ld, wscale, hm.W.data());
-    else fill_padded<int32_t>(Q, n, ld, wscale, hm.W.data());
+    std::vector<int64_t> row(n, 0);
+    if (dtype == 1) fill_padded<int8_t>(Q, n, ld, wscale, hm.W.data(), row);
+    else if (dtype == 2) fill_padded<int16_t>(Q, n, ld, wscale, hm.W.data(), row);
+    else fill_padded<int32_t>(Q, n, ld, wscale, hm.W.data(), row);
     hm.b.assign(ld, 0);
-    for (size_t i = 0; i < n; ++i) hm.b[i] = Q[i * n + i];
+    hm.hbound = 0;
+    for (size_t i = 0; i < n; ++i) {
+        hm.b[i] = Q[i * n + i];
+        hm.hbound = std::max(hm.hbound, row[i] + (hm.b[i] < 0 ? -(int64_t)hm.b[i] : hm.b[i]));
+    }
 }
 
 int prepare_sparse(const int32_t *Q, int32_t N, HostMatrix &hm, std::string &err) {
@@ -503,6 +526,7 @@ int create_ctx(const HostMatrix &hm, hipStream_t s, da_ctx **out, std::string &e
     ctx->ld = hm.ld;
     ctx->dtype = hm.dtype;
     ctx->wscale = hm.wscale;
+    ctx->hbound = hm.hbound;
     const char *what = nullptr;
     hipError_t e = hipGetDevice(&ctx->device);
     if (e != hipSuccess) what = "device query";
@@ -596,7 +620,7 @@ int tuned_shape(da_ctx *ctx, const LevelTables &lt, int32_t R, int64_t steps,
     hipEvent_t a = nullptr, b = nullptr;
     rc = check_hip(ctx, hipEventCreate(&a), "autotuner: event create");
     if (!rc) rc = check_hip(ctx, hipEventCreate(&b), "autotuner: event create");
-    da_launch best{0, 0, 0, 0};
+    da_launch best{0, 0, 0, 0, 0};
     float best_ms = 1e30f;
     // W staged in LDS is a candidate whenever it fits there
     const bool w_fits = ctx->ell_D == 0 &&
@@ -605,14 +629,17 @@ int tuned_shape(da_ctx *ctx, const LevelTables &lt, int32_t R, int64_t steps,
         if (F == 2 && ctx->dtype > 2) continue;
         for (int rpw : {1, 2, 4}) {
             for (int rng : {1, -1})
-            for (int wl : {-1, 1}) {
+            for (int wl : {-1, 1})
+            for (int ge : {1, -1}) {
                 if (rc) break;
                 if (wl > 0 && !w_fits) continue;
-                const da_launch cand{F, rpw, wl, rng};
+                const da_launch cand{F, rpw, wl, rng, ge};
                 const LaunchShape sh = choose_shape(ctx, R, &cand, true, direct);
                 if (sh.RPW != rpw || sh.F != F || sh.w_lds != (wl > 0 ? 1 : 0) ||
                     sh.threads > 1024 || sh.lds > (size_t)device_lds_limit())
                     continue;
+                // the estimate candidate only where the shape can take it
+                if (ge > 0 && (!sh.gen || !lt.any_gth)) continue;
                 JobDesc J = make_job(ctx, lt, R, 0u, 1u, steps, sched, sh);
                 tune_window(steps, J.s0, J.s1);
                 if (const char *why = job_range_error(J)) {
@@ -624,7 +651,8 @@ int tuned_shape(da_ctx *ctx, const LevelTables &lt, int32_t R, int64_t steps,
                 char what[160];
                 std::snprintf(what, sizeof what,
                               "autotuner candidate (flips/lane %d, replicas/workgroup %d, "
-                              "rng waves %d, W in LDS %d)", F, rpw, rng, wl);
+                              "rng waves %d, W in LDS %d, draw estimates %d)", F, rpw, rng, wl,
+                              ge);
                 rc = check_hip(ctx, (hipError_t)launch_state_zero(J, s), what);
                 if (!rc) rc = check_hip(ctx, hipEventRecord(a, s), what);
                 if (!rc)
@@ -743,7 +771,7 @@ int copy_outputs_to_host(da_ctx *ctx, const JobDesc &J, int32_t R, const da_resu
     return check_hip(ctx, e, "copy of outputs to host");
 }
 
-void record_stats(da_ctx *ctx, const LaunchShape &sh, int64_t launches) {
+void record_stats(da_ctx *ctx, const LaunchShape &sh, int64_t launches, int gth = 0) {
     (void)launches;
     ctx->last = da_kernel_stats{};
     ctx->last.blocks = sh.blocks;
@@ -753,6 +781,7 @@ void record_stats(da_ctx *ctx, const LaunchShape &sh, int64_t launches) {
     ctx->last.w_in_lds = sh.w_lds;
     ctx->last.rng_waves = sh.NH;
     ctx->last.dtype = ctx->dtype;
+    ctx->last.draw_estimates = gth;
     ctx->have_stats = true;
 }
 
@@ -858,7 +887,7 @@ int enqueue_anneal(da_ctx *ctx, const da_schedule *schedule, int64_t replica_bas
     }
     rc = check_hip(ctx, hipEventRecord(e1, s), "event record");
     if (rc) return rc;
-    record_stats(ctx, sh, 1);
+    record_stats(ctx, sh, 1, J.gth);
     ctx->st_step = step_end;
     ctx->st_base = replica_base;
     ctx->st_R = replicas;

@@ -35,14 +35,32 @@ namespace dapt {
 // The table depends on the draw only, so it can be read before the flip's
 // cost is known.  Such levels also have |tmin| <= kDirectTmin (always true of
 // a narrow band, as thr >= -1; stated so that tmin + 1 + E_off + q fits int32).
+//
+// Wide bands can also be decided from a per-draw estimate computed by the
+// random-number waves (kernel variant kModeGen): G(u) = trunc(fma(log2(u + 1/2),
+// ga, gb)) in fp32 with ga = T ln 2 and gb = -16 T ln 2, so that -G(u) is within
+// a few units of thr[u].  A device pass over all 65536 draws measures, with the
+// kernel's own instructions, off(u) = thr[u] + G(u) and keeps its range
+// [glo, ghi], so thr[u] lies in [glo - G(u), ghi - G(u)] for every draw:
+// d <= glo - G(u) accepts, d > ghi - G(u) rejects, and only the rare d in
+// between (a window of ghi - glo values) reads thr[u].  gth = 1 marks a level
+// whose window was measured and is at most kGenWindow wide.
 struct LevelHdr {
     int32_t tmin;
     int32_t tmax;
     int32_t sh;
     int32_t off;   // first bucket of this level in brk
     int32_t q8;    // index of this level's direct table, or -1
-    int32_t pad[3];
+    int32_t gth;   // per-draw estimate usable (set by the measuring pass)
+    float ga, gb;  // estimate coefficients (T ln 2, -16 T ln 2)
+    int32_t glo, ghi;   // range of thr[u] + G(u) over all draws
+    int32_t pad[2];
 };
+constexpr int kGenWindow = 64;      // widest measured window a level may use
+constexpr int kGenOffMax = 64;      // and |glo|, |ghi| at most this
+// the estimate path keeps d - glo + G(u) - 1 in int32 when |h| stays below
+// this bound and tmax < 2^29
+constexpr int64_t kGenFieldMax = (int64_t(1) << 29) - 256;
 constexpr int kDirectSpan = 255;
 constexpr int kDirectTmin = 256;
 constexpr int kMaxDirectLevels = 512;   // schedules with more levels use brackets only
@@ -64,7 +82,7 @@ struct StepT {
 
 // Compile-time feature sets of the step kernel (see run_block).
 constexpr int kModePlain = 0, kModeSingle = 1, kModePerStep = 2, kModeDynamic = 4,
-              kModeSparse = 8, kModeWide = 16, kModeDirect = 32;
+              kModeSparse = 8, kModeWide = 16, kModeDirect = 32, kModeGen = 64;
 
 struct JobDesc {
     const void *W;
@@ -99,6 +117,7 @@ struct JobDesc {
     int32_t single;              // 1: only variable s mod N proposes at step s
     int32_t ell_D;               // sparse row lists: entries per row (0: dense)
     const uint32_t *ell;         // [N][ell_D] column | value << 16, or null
+    int32_t gth;                 // 1: random-number waves hand over per-draw estimates
 };
 
 constexpr int64_t kMaxPerStepSteps = int64_t(1) << 24;
@@ -181,10 +200,10 @@ int device_lds_limit();
 // double-buffered Philox blocks; with sparse row lists (dhF = flips per lane)
 // one field-delta buffer of 64 * dhF int32 per compute wave.
 struct SlotLayout {
-    int rec, dEs, vring, draws, dh, bytes;
+    int rec, dEs, vring, draws, dh, est, bytes;
 };
-__host__ __device__ inline SlotLayout slot_layout(int NW, int NH, int dhF = 0) {
-    SlotLayout L{0, 0, 0, 0, 0, 0};
+__host__ __device__ inline SlotLayout slot_layout(int NW, int NH, int dhF = 0, bool gen = false) {
+    SlotLayout L{0, 0, 0, 0, 0, 0, 0};
     int off = 0;
     if (NW > 1 || NH > 0) {
         // lane records [2][max(NW, 4) * 64]: four waves' records can always be
@@ -200,6 +219,12 @@ __host__ __device__ inline SlotLayout slot_layout(int NW, int NH, int dhF = 0) {
         off = (off + 15) & ~15;
         L.draws = off;
         off += 2 * NH * 64 * 16;
+        if (gen) {
+            // per-draw estimates G(u) of each step, [2][2][NH * 64] int4: part 0
+            // holds a block's draws 0..3, part 1 its draws 4..7
+            L.est = off;
+            off += 2 * 2 * NH * 64 * 16;
+        }
     }
     if (dhF > 0) {
         off = (off + 15) & ~15;
@@ -214,6 +239,9 @@ __host__ __device__ inline SlotLayout slot_layout(int NW, int NH, int dhF = 0) {
 // level's bracket table is staged in LDS, anneal mode; direct: so is a direct
 // table of 65536 bytes).
 size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk, int NH,
-                     bool sparse = false, bool direct = false);
+                     bool sparse = false, bool direct = false, bool gen = false);
+// Measures glo/ghi of every level marked gth in hdr (device, [L]) against the
+// threshold tables thr [L][65536], and clears gth where the window is too wide.
+int launch_gen_calibrate(LevelHdr *hdr, const int32_t *thr, int32_t L, void *stream);
 
 }  // namespace dapt

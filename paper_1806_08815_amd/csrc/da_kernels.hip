@@ -92,6 +92,18 @@ __device__ __forceinline__ uint32_t philox_x_uniform(uint32_t c0, uint32_t c1, u
     return c0;
 }
 
+// Per-draw estimate G(u) ~ -thr[u] of a level (coefficients ga = T ln 2,
+// gb = -16 T ln 2): -T ln((u + 1/2) / 65536) evaluated as an fp32 base-2
+// logarithm and one fused multiply-add, truncated.  Any deterministic
+// function would do: the window pass below measures thr[u] + G(u) over every
+// draw with these same instructions, and decisions only use G inside that
+// measured bracket.
+__device__ __forceinline__ int draw_estimate(uint32_t u, float ga, float gb) {
+    const float x = (float)u + 0.5f;                 // exact for u < 2^16
+    const float lg = __builtin_amdgcn_logf(x);       // v_log_f32
+    return (int)__builtin_fmaf(lg, ga, gb);
+}
+
 __device__ __forceinline__ uint32_t word_of(const uint4 &v, int w) {
     return w == 0 ? v.x : (w == 1 ? v.y : (w == 2 ? v.z : v.w));
 }
@@ -222,8 +234,8 @@ __device__ __forceinline__ int row16_incl_scan(int v) {
 }  // namespace
 
 size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk, int NH,
-                     bool sparse, bool direct) {
-    const SlotLayout SL = slot_layout(NW, NH, sparse ? F : 0);
+                     bool sparse, bool direct, bool gen) {
+    const SlotLayout SL = slot_layout(NW, NH, sparse ? F : 0, gen);
     size_t w = (size_t)((w_lds_bytes + 15) & ~15);
     size_t b = stage_brk ? (size_t)kMaxBuckets * 4 + (direct ? 65536 : 0) : 0;
     return w + b + (size_t)SL.bytes * RPW;
@@ -327,7 +339,10 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     constexpr bool dq = (MODE & kModeDirect) != 0;
     const bool has_q = dq && stage && !perstep && J.q8 != nullptr;
     const uint8_t *q_l = smem + w_bytes + kMaxBuckets * 4;
-    const SlotLayout SL = slot_layout(NW, NH, sparse ? F : 0);
+    // per-draw estimates handed over by the random-number waves (wide bands)
+    constexpr bool gen = (MODE & kModeGen) != 0;
+    static_assert(!gen || (HELP && F >= 4 && !BATCH), "estimates come from random-number waves");
+    const SlotLayout SL = slot_layout(NW, NH, sparse ? F : 0, gen);
     uint8_t *sel = smem + w_bytes + (stage ? kMaxBuckets * 4 + (has_q ? 65536 : 0) : 0) +
                    (size_t)SL.bytes * slot;
     // lane records by step parity; a wave's total is its last lane's prefix
@@ -336,6 +351,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     int *dEs = reinterpret_cast<int *>(sel + SL.dEs);              // [2]
     uint32_t *vring = reinterpret_cast<uint32_t *>(sel + SL.vring);  // [4] selection draws
     uint4 *draws = reinterpret_cast<uint4 *>(sel + SL.draws);      // [2][NH*64] Philox blocks
+    int4 *est = reinterpret_cast<int4 *>(sel + SL.est);            // [2][2][NH*64] estimates
     // sparse rows: this wave's field-delta buffer [64 * F], kept all zero between steps
     int *dh = reinterpret_cast<int *>(sel + SL.dh) + (helper ? 0 : wr) * 64 * F;
     if (sparse && !helper) {
@@ -443,12 +459,34 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         for (int f = 0; f < F; ++f) q[f] = q_l[draw16(r, f)];
     };
 
-    // generator waves: the draws of step st into ring slot st & 1
+    // generator waves: the estimate coefficients of the level of the step
+    // they produce (kept in scalar registers; updated when that step opens a
+    // new level)
+    int ggth = hd.gth;
+    float gga = hd.ga, ggb = hd.gb;
+    // generator waves: the draws of step st into ring slot st & 1, with the
+    // per-draw estimates where its level uses them
     auto produce = [&](int64_t st) {
         const int b = g;   // Philox block of this generator lane
-        if (active && b < nblk)
-            draws[(int)(st & 1) * NH * 64 + b] =
-                philox((uint32_t)b, (uint32_t)st, rid, kTagMetropolis, k0, k1);
+        if (active && b < nblk) {
+            const uint4 r = philox((uint32_t)b, (uint32_t)st, rid, kTagMetropolis, k0, k1);
+            draws[(int)(st & 1) * NH * 64 + b] = r;
+            if (gen && ggth) {
+                // draw 2q of the block is the low half of word q, 2q + 1 the high half
+                int4 e0, e1;
+                e0.x = draw_estimate(r.x & 0xFFFFu, gga, ggb);
+                e0.y = draw_estimate(r.x >> 16, gga, ggb);
+                e0.z = draw_estimate(r.y & 0xFFFFu, gga, ggb);
+                e0.w = draw_estimate(r.y >> 16, gga, ggb);
+                e1.x = draw_estimate(r.z & 0xFFFFu, gga, ggb);
+                e1.y = draw_estimate(r.z >> 16, gga, ggb);
+                e1.z = draw_estimate(r.w & 0xFFFFu, gga, ggb);
+                e1.w = draw_estimate(r.w >> 16, gga, ggb);
+                int4 *dst = est + (int)(st & 1) * 2 * NH * 64;
+                dst[b] = e0;
+                dst[NH * 64 + b] = e1;
+            }
+        }
         if (active && wr == NH - 1) {
             const uint32_t v = philox_x_uniform(0u, (uint32_t)st, rid, kTagSelect, k0, k1);
             if (lane == 0) vring[(int)(st & 3)] = v;
@@ -472,7 +510,27 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         }
     };
 
+    // compute waves: this lane's per-draw estimates of step st
+    auto read_est = [&](int64_t st, int (&dst)[F]) {
+        const int4 *src = est + (int)(st & 1) * 2 * NH * 64;
+        if constexpr (!gen) {
+            (void)src;
+        } else if constexpr (F >= 8) {
+            const int q = min(g, NH * 64 - 1);
+            const int4 a = src[q], b = src[NH * 64 + q];
+            dst[0] = a.x; dst[1] = a.y; dst[2] = a.z; dst[3] = a.w;
+            dst[4] = b.x; dst[5] = b.y; dst[6] = b.z; dst[7] = b.w;
+        } else {
+            // four flips per lane: half a block, part g & 1 of block g >> 1
+            const int4 a = src[(g & 1) * NH * 64 + min(g >> 1, NH * 64 - 1)];
+            dst[0] = a.x; dst[1] = a.y; dst[2] = a.z; dst[3] = a.w;
+        }
+    };
+
     uint4 rb[NB];
+    int tv[F];   // this step's per-draw estimates (kModeGen)
+#pragma unroll
+    for (int f = 0; f < F; ++f) tv[f] = 0;
     // with random-number waves the direct-table decisions of a step are read
     // one step ahead, as soon as its draws arrive
     uint32_t qv[F];
@@ -484,6 +542,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         if (!helper) {
             consume(s0, rb);
             if (direct) lookup_q(rb, qv);
+            if (gen) read_est(s0, tv);
         }
     }
 
@@ -508,7 +567,17 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 hd = J.hdr[lvl];
                 if (stage) stage_brackets();
             }
-            if (left != 1) produce(s + 1);
+            if (left != 1) {
+                // step s + 1 may open the next level: its estimates use that one
+                if (gen && to_next == 1) {
+                    const int ln = __builtin_amdgcn_readfirstlane(level_of(s + 1, J.L, J.S));
+                    const LevelHdr hn = J.hdr[ln];
+                    ggth = __builtin_amdgcn_readfirstlane(hn.gth);
+                    gga = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(hn.ga)));
+                    ggb = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(hn.gb)));
+                }
+                produce(s + 1);
+            }
             __syncthreads();
         }
     }
@@ -538,7 +607,47 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         uint32_t acc = 0;
         int c = 0, excl = 0, wtot = 0;
 
-        if (fast) {
+        if (gen && hd.gth && full) {
+            // wide band with per-draw estimates G(u): thr[u] lies in
+            // [glo - G, ghi - G], so with z = d - glo + G - 1 (d = (1 - 2x) h -
+            // E_off) a flip is accepted when z < 0, rejected when z >= ghi - glo,
+            // and only in between is thr[u] read.  The host allows this path
+            // only for |h| <= kGenFieldMax and levels with tmax < 2^29 and
+            // |glo|, |ghi| <= kGenOffMax, so z stays in int32.  The sign bits of
+            // z shift straight into the accepted mask.
+            const int Ec = eoff + hd.glo + 1;
+            const uint32_t Wt = (uint32_t)(hd.ghi - hd.glo);
+            uint32_t zmin = 0xFFFFFFFFu;
+            int zv[F];
+#pragma unroll
+            for (int f = F - 1; f >= 0; --f) {
+                const int mx = -(int)((xb >> f) & 1u);
+                const int z = ((h[f] ^ mx) - mx) + tv[f] - Ec;
+                zv[f] = z;
+                acc = __builtin_amdgcn_alignbit(acc, (uint32_t)z, 31);
+                zmin = min(zmin, (uint32_t)z);
+            }
+            if (ballot(zmin < Wt)) {
+                // a flip inside the window (rare): the exact table entry.  This
+                // step's draws are still in ring slot s & 1.
+                uint4 rt[NB];
+                consume(s, rt);
+                const int32_t *thr = J.thr + (size_t)lvl * 65536;
+                int t[F];
+#pragma unroll
+                for (int f = 0; f < F; ++f)
+                    t[f] = thr[((uint32_t)zv[f] < Wt) ? draw16(rt, f) : 0u];
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    const int mx = -(int)((xb >> f) & 1u);
+                    const int dd = ((h[f] ^ mx) - mx) - eoff;
+                    acc |= (uint32_t)(((uint32_t)zv[f] < Wt) & (dd <= t[f])) << f;
+                }
+            }
+            c = __popc(acc);
+            wave_prefix<CountBits<F>::value>(c, excl, wtot);
+            if (NW > 1) rec[par * RS + g] = acc | (xb << 8) | ((uint32_t)(excl + c) << 16);
+        } else if (fast) {
             // 1-3a, narrow band with the decisions' table entries already read:
             // with s = (1 - 2x) h the flip is accepted iff s - E_off <= thr[u]
             // = tmin + q[u], i.e. s < q[u] + c with c = tmin + 1 + E_off.  As
@@ -717,6 +826,8 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         // (on the last step these read draws no step uses: stale, in bounds)
         uint4 rbn[NB];
         if (HELP) consume(s + 1, rbn);
+        int tvn[F];
+        if (gen) read_est(s + 1, tvn);
         const uint32_t vs = HELP ? vring[(int)(s & 3)] : 0u;
         int dEp = 0, tw = 0;
         uint32_t r4[4] = {0u, 0u, 0u, 0u};
@@ -733,6 +844,10 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                          "v"(dEp));
         } else if (HELP) {
             asm volatile("" ::"v"(vs));
+        }
+        if (gen) {
+#pragma unroll
+            for (int f = 0; f < F; ++f) asm volatile("" ::"v"(tvn[f]));
         }
         int m, k = 0, xk = 0, dk = 0, bit = 0;
         if (NW == 1) {
@@ -887,6 +1002,10 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         if (HELP) {
 #pragma unroll
             for (int q = 0; q < NB; ++q) rb[q] = rbn[q];
+        }
+        if (gen) {
+#pragma unroll
+            for (int f = 0; f < F; ++f) tv[f] = tvn[f];
         }
         if (single) prop = (prop + 1 == J.N) ? 0 : prop + 1;
         if (TRACE && active && g == 0) {
@@ -1298,6 +1417,44 @@ __global__ void k_fill_i32(int32_t *dst, int32_t value, int64_t n) {
         dst[q] = value;
 }
 
+// Window of the per-draw estimate of every candidate level: the range of
+// thr[u] + G(u) over all 65536 draws (one workgroup per level).  A level keeps
+// gth only if the window is narrow and near zero, which also keeps the step
+// kernel's sums in int32.
+__global__ __launch_bounds__(256) void k_gen_calibrate(LevelHdr *hdr, const int32_t *thr,
+                                                       int32_t L) {
+    __shared__ int s_lo[256], s_hi[256];
+    const int l = blockIdx.x;
+    if (l >= L) return;
+    const LevelHdr hd = hdr[l];
+    if (!hd.gth) return;
+    const int32_t *t = thr + (size_t)l * 65536;
+    int lo = INT32_MAX, hi = INT32_MIN;
+    for (int u = threadIdx.x; u < 65536; u += blockDim.x) {
+        const int off = t[u] + draw_estimate((uint32_t)u, hd.ga, hd.gb);
+        lo = min(lo, off);
+        hi = max(hi, off);
+    }
+    s_lo[threadIdx.x] = lo;
+    s_hi[threadIdx.x] = hi;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s_lo[threadIdx.x] = min(s_lo[threadIdx.x], s_lo[threadIdx.x + w]);
+            s_hi[threadIdx.x] = max(s_hi[threadIdx.x], s_hi[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        lo = s_lo[0];
+        hi = s_hi[0];
+        const bool ok = lo >= -kGenOffMax && hi <= kGenOffMax && hi - lo <= kGenWindow;
+        hdr[l].glo = ok ? lo : 0;
+        hdr[l].ghi = ok ? hi : 0;
+        hdr[l].gth = ok ? 1 : 0;
+    }
+}
+
 // --------------------------------------------------------------------------
 // Host launch wrappers.
 // --------------------------------------------------------------------------
@@ -1372,6 +1529,13 @@ int launch_run_t(const JobDesc &J, const TraceDesc &T, int blocks, int threads, 
     }
     switch (mode) {
         case kModePlain:
+            if constexpr (HELP && F >= 4) {
+                if (J.gth && wide && !J.q8) {
+                    hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, kModeWide | kModeGen>), g,
+                                       b, lds, S(stream), J, T);
+                    break;
+                }
+            }
             if (J.q8 && wide)
                 hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, kModeWide | kModeDirect>), g,
                                    b, lds, S(stream), J, T);
@@ -1529,6 +1693,12 @@ int launch_copy_i64(const int64_t *src, int64_t *dst, int32_t n, void *stream) {
 
 int launch_fill_i32(int32_t *dst, int32_t value, int64_t n, void *stream) {
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256)), dim3(256), 0, S(stream), dst, value, n);
+    return (int)hipGetLastError();
+}
+
+int launch_gen_calibrate(LevelHdr *hdr, const int32_t *thr, int32_t L, void *stream) {
+    if (L < 1 || !hdr || !thr) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gen_calibrate, dim3(L), dim3(256), 0, S(stream), hdr, thr, L);
     return (int)hipGetLastError();
 }
 

@@ -24,7 +24,8 @@ struct LevelTables {
     uint32_t *d_brk = nullptr;     // brackets of all levels
     uint8_t *d_q8 = nullptr;       // direct tables [levels with q8 >= 0][65536], or null
     size_t bytes = 0;
-    std::vector<LevelHdr> hdr;     // host copy (tests, footprints)
+    std::vector<LevelHdr> hdr;     // host copy (tests, footprints), estimate windows included
+    bool any_gth = false;          // some level can be decided from per-draw estimates
     ~LevelTables();
 };
 
@@ -97,6 +98,7 @@ struct LaunchShape {
     int RPW = 1;
     int w_lds = 0;
     int direct = 0;     // the level's direct table is staged in LDS (anneal mode)
+    int gen = 0;        // random-number waves may hand over per-draw estimates
     int threads = 64;
     int blocks = 1;
     size_t lds = 0;
@@ -146,6 +148,7 @@ int derive_storage(const int32_t *Q, int32_t N, int32_t dtype_hint, int32_t &dty
 // bytes per coupling; b = diag(Q), zero padded.
 struct HostMatrix {
     int32_t N = 0, ld = 0, dtype = 0, wscale = 1;
+    int64_t hbound = 0;            // max_i |b_i| + sum_j |W_ij|: bounds every |h_i|
     std::vector<uint8_t> W;
     std::vector<int32_t> b;
     int32_t ell_D = 0;             // sparse row lists: D entries per row, 0 = none
@@ -169,6 +172,7 @@ struct da_ctx {
     int32_t wscale = 1;
     int device = 0;
     int cus = 256;               // compute units of the device
+    int64_t hbound = 0;          // bound of every |h_i| (max_i |b_i| + sum_j |W_ij|)
     void *d_W = nullptr;
     int32_t *d_b = nullptr;
     uint32_t *d_ell = nullptr;   // sparse row lists [N][ell_D], or null

@@ -3,9 +3,10 @@
 // The Metropolis acceptance exp(-dE/T) (Sec. III of arXiv:1806.08815) is
 // decided in integers.  A 16-bit draw u stands for U_u = (u + 1/2)/65536, and a
 // flip of offset-shifted cost d is accepted iff U_u < exp(-d/T), which for an
-// integer d is d <= thr[u] with thr[u] = ceil(-T ln U_u) - 1.  The device
-// never evaluates a logarithm: it compares against these host-built tables,
-// so the decision is bit-identical wherever it is made.
+// integer d is d <= thr[u] with thr[u] = ceil(-T ln U_u) - 1.  Every decision
+// the device takes is this comparison against these host-built tables, so it
+// is bit-identical wherever it is made; the device's own fp32 estimate of
+// thr[u] (LevelHdr) only brackets it, with a window measured over all draws.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -63,7 +64,10 @@ void build_brackets(const int32_t *thr, LevelHdr &hd, std::vector<uint32_t> &brk
     hd.tmax = thr[0];
     hd.sh = 0;
     hd.q8 = -1;
-    hd.pad[0] = hd.pad[1] = hd.pad[2] = 0;
+    hd.gth = 0;
+    hd.ga = hd.gb = 0.0f;
+    hd.glo = hd.ghi = 0;
+    hd.pad[0] = hd.pad[1] = 0;
     hd.off = (int32_t)brk.size();
     // every level ends with a reject-all entry (lo = hi = 0), which costs
     // past the last bucket may read
@@ -147,6 +151,14 @@ void build_host_tables(const std::vector<double> &temps, HostTables &ht) {
             hd.q8 = nq++;
             for (int u = 0; u < 65536; ++u) ht.q8.push_back((uint8_t)(thr[u] - hd.tmin));
         }
+        // candidates for the per-draw estimate: -G(u) ~ T ln(65536 / (u + 1/2));
+        // the device measures the window (launch_gen_calibrate)
+        const double T = temps[l];
+        if (T > 0.0 && std::isfinite(T) && hd.tmax < (1 << 29)) {
+            hd.gth = 1;
+            hd.ga = (float)(T * std::log(2.0));
+            hd.gb = (float)(-16.0 * T * std::log(2.0));
+        }
     }
     if (ht.brk.empty()) ht.brk.push_back(0);
 }
@@ -190,6 +202,15 @@ std::shared_ptr<LevelTables> get_level_tables(const std::vector<double> &temps, 
         err = "upload of level tables failed";
         return nullptr;
     }
+    // windows of the per-draw estimates, measured on this device; the host
+    // copy of the headers takes them over
+    if (launch_gen_calibrate(lt->d_hdr, lt->d_thr, lt->L, nullptr) != hipSuccess ||
+        hipStreamSynchronize(nullptr) != hipSuccess ||
+        hipMemcpy(lt->hdr.data(), lt->d_hdr, hdr_b, hipMemcpyDeviceToHost) != hipSuccess) {
+        err = "estimate window pass over the level tables failed";
+        return nullptr;
+    }
+    for (const LevelHdr &h : lt->hdr) lt->any_gth = lt->any_gth || h.gth != 0;
     lt->bytes = thr_b + hdr_b + brk_b + q8_b;
     g_cache[key] = lt;
     return lt;

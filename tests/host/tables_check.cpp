@@ -60,6 +60,32 @@ static bool one_read_form(const int32_t *thr, const LevelHdr &hd, const uint32_t
     return acc;
 }
 
+// The per-draw estimate path (kModeGen) with an estimate G of the device's
+// form evaluated on the host (the host's log2f stands in for v_log_f32; the
+// window is measured over all draws either way): with z = s + G(u) - (E_off +
+// glo + 1) in wrapping int32 arithmetic, z < 0 accepts, ghi - glo <= z rejects,
+// and in between the exact entry decides.  Also checks that z never wraps for
+// |s| <= kGenFieldMax, E_off in [0, 2^30] and tmax < 2^29.
+static int host_estimate(uint32_t u, float ga, float gb) {
+    const float x = (float)u + 0.5f;
+    return (int)std::fma(std::log2(x), ga, gb);
+}
+
+static bool estimate_form(const int32_t *thr, int glo, int ghi, int32_t G, int64_t s, int32_t eoff,
+                          uint32_t u, bool &wrapped) {
+    const int32_t Ec = (int32_t)((uint32_t)eoff + (uint32_t)glo + 1u);
+    const int32_t z = (int32_t)((uint32_t)(int32_t)s + (uint32_t)G - (uint32_t)Ec);
+    wrapped = (int64_t)z != s + (int64_t)G - (int64_t)Ec;
+    if (z < 0) return true;
+    if ((uint32_t)z >= (uint32_t)(ghi - glo)) return false;
+    return s - eoff <= thr[u];
+}
+
+// never called here: the host check builds tables without uploading them
+namespace dapt {
+int launch_gen_calibrate(LevelHdr *, const int32_t *, int32_t, void *) { return 1; }
+}  // namespace dapt
+
 int main() {
     std::vector<std::vector<double>> lists;
     for (double Thi : {0.3, 3.0, 20.0, 60.0, 196608.0, 1e6, 3e8, 5e9})
@@ -114,6 +140,50 @@ int main() {
                     if (q && d >= -(int64_t(1) << 30) - (int64_t(1) << 30) + 512)
                         CHECK(((d - ((int64_t)hd.tmin + 1)) < (int64_t)q[u]) == want,
                               "T=%g d=%lld u=%u: direct table", t[l], (long long)d, u);
+                }
+            // the estimate path: candidates are exactly the levels with T > 0
+            // and tmax < 2^29; window measured over every draw
+            CHECK(hd.gth == ((t[l] > 0.0 && hd.tmax < (1 << 29)) ? 1 : 0), "T=%g: estimate flag",
+                  t[l]);
+            if (!hd.gth) continue;
+            int glo = INT32_MAX, ghi = INT32_MIN;
+            std::vector<int32_t> G(65536);
+            for (uint32_t u = 0; u < 65536; ++u) {
+                G[u] = host_estimate(u, hd.ga, hd.gb);
+                glo = std::min(glo, thr[u] + G[u]);
+                ghi = std::max(ghi, thr[u] + G[u]);
+            }
+            // the device keeps a level only when its window is narrow (fp32
+            // rounding widens it with T: a few units up to T ~ 1e6)
+            const bool ok = glo >= -kGenOffMax && ghi <= kGenOffMax && ghi - glo <= kGenWindow;
+            if (t[l] <= 1e6)
+                CHECK(ok && ghi - glo <= 4, "T=%g: estimate window [%d, %d]", t[l], glo, ghi);
+            if (!ok) continue;
+            for (int32_t eoff : {0, 1, 1 << 20, 1 << 29, (1 << 30) - 1, 1 << 30})
+                for (int64_t d : ds) {
+                    const int64_t s = d + eoff;
+                    if (s > kGenFieldMax || s < -kGenFieldMax) continue;
+                    for (int k = 0; k < 3; ++k) {
+                        const uint32_t u =
+                            k == 0 ? 0u : (k == 1 ? 65535u : (uint32_t)(rng() & 0xFFFFu));
+                        bool wrapped = false;
+                        ++decisions;
+                        CHECK(estimate_form(thr, glo, ghi, G[u], s, eoff, u, wrapped) ==
+                                  (d <= thr[u]),
+                              "T=%g d=%lld eoff=%d u=%u: estimate form", t[l], (long long)d,
+                              eoff, u);
+                        CHECK(!wrapped, "T=%g s=%lld eoff=%d: estimate sum wraps", t[l],
+                              (long long)s, eoff);
+                    }
+                }
+            // the extreme sums: |s| at the bound, largest offset, both ends of G
+            for (int64_t s : {-kGenFieldMax, kGenFieldMax})
+                for (uint32_t u : {0u, 65535u}) {
+                    bool wrapped = false;
+                    (void)estimate_form(thr, glo, ghi, G[u], s, 1 << 30, u, wrapped);
+                    CHECK(!wrapped, "T=%g: extreme estimate sum wraps", t[l]);
+                    (void)estimate_form(thr, glo, ghi, G[u], s, 0, u, wrapped);
+                    CHECK(!wrapped, "T=%g: extreme estimate sum wraps", t[l]);
                 }
         }
     }

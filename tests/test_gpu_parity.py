@@ -121,18 +121,79 @@ def test_direct_table_trace_parity(api, kind, N, dtype, F, rpw, rng):
     (1024, 0, 8, 1), (1000, 0, 8, 1), (300, 4, 4, 2), (513, 0, 8, 1), (2048, 0, 8, 1), (64, 0, 4, 1),
 ])
 def test_wide_band_trace_parity(api, N, dtype, F, rpw):
-    """Gaussian couplings with random-number waves: every level's band is wide
-    (buckets of 2^sh costs), so full waves decide each flip by one bracket read
-    (costs past the buckets meet the reject-all entry) and waves holding ghost
-    flips take the band tests; N = 1000, 300 and 513 mix both in one replica."""
+    """Gaussian couplings with random-number waves and no per-draw estimates:
+    every level's band is wide (buckets of 2^sh costs), so full waves decide
+    each flip by one bracket read (costs past the buckets meet the reject-all
+    entry) and waves holding ghost flips take the band tests; N = 1000, 300 and
+    513 mix both in one replica."""
     Q = _q("gauss", N, 5)
     T_hi, T_lo, inc = 3.0 * 2**16, 0.05 * 2**16, 2**16
     R, S, L = 5, 1200, 6
     ctx = api.da_create(Q, dtype)
     sch = api.schedule(T_hi, T_lo, "geometric", L, eoff_inc=inc)
-    gpu = api.da_anneal_ex(ctx, sch, 3, R, S, 11, api.launch(F, rpw, 0, 1), trace=True)
+    gpu = api.da_anneal_ex(ctx, sch, 3, R, S, 11, api.launch(F, rpw, 0, 1, -1), trace=True)
+    assert api.da_last_kernel_stats(ctx)["draw_estimates"] == 0
     ref = oracle.anneal(Q, T_hi=T_hi, T_lo=T_lo, n_levels=L, eoff_inc=inc, replica_base=3,
                         replicas=R, steps=S, seed=11, trace=True)
+    _same(gpu, ref, ("trace_k", "trace_E", "trace_eoff") + KEYS)
+
+
+@pytest.mark.parametrize("kind,N,dtype,F,rpw,init", [
+    ("gauss", 1024, 0, 8, 1, 0), ("gauss", 1024, 0, 4, 1, 1), ("gauss", 1000, 0, 8, 1, 0),
+    ("gauss", 300, 4, 4, 2, 1), ("gauss", 513, 0, 8, 1, 0), ("gauss", 2048, 0, 8, 1, 0),
+    ("gauss", 4096, 2, 8, 1, 1), ("sk", 1024, 0, 8, 1, 0), ("sk", 1000, 1, 4, 2, 1),
+    ("sk", 300, 0, 4, 4, 0), ("random", 777, 0, 4, 1, 1),
+])
+def test_draw_estimate_trace_parity(api, kind, N, dtype, F, rpw, init):
+    """Per-draw estimates: the random-number waves hand over G(u) ~ -thr[u] and
+    full waves decide each flip by the sign of d - glo + G(u) - 1, reading
+    thr[u] only inside the measured window.  Gaussian levels are wide; the
+    +-1 and small-integer instances have levels of a few units, so costs sit
+    inside the window often and the exact reads run many times per step.
+    Short levels keep the direct tables off, so every level takes the
+    estimates; ragged N mixes full waves with band-test waves."""
+    Q = _q(kind, N, 13)
+    if kind == "gauss":
+        T_hi, T_lo, inc = 3.0 * 2**16, 0.05 * 2**16, 2**16
+    else:
+        T_hi, T_lo, inc = 3.0 * max(1.0, N ** 0.5), 0.1, 1
+    R, S, L = 4, 1500, 12   # levels of 125 steps: no direct tables
+    ctx = api.da_create(Q, dtype)
+    sch = api.schedule(T_hi, T_lo, "geometric", L, eoff_inc=inc, init=init)
+    gpu = api.da_anneal_ex(ctx, sch, 2, R, S, 29, api.launch(F, rpw, 0, 1, 1), trace=True)
+    assert api.da_last_kernel_stats(ctx)["draw_estimates"] == 1
+    ref = oracle.anneal(Q, T_hi=T_hi, T_lo=T_lo, n_levels=L, eoff_inc=inc, init=init,
+                        replica_base=2, replicas=R, steps=S, seed=29, trace=True)
+    _same(gpu, ref, ("trace_k", "trace_E", "trace_eoff") + KEYS)
+
+
+@pytest.mark.parametrize("over", [False, True])
+def test_draw_estimate_field_bound(api, over):
+    """Fields at the estimate path's bound: row 0's |b_0| + sum_j |W_0j| is
+    exactly 2^29 - 256 (one more with over), random starts put fields near it
+    at once, tmax sits just under 2^29 and the offset saturates at 2^30, so
+    d - glo + G(u) - 1 reaches the int32 ends.  Over the bound the host keeps
+    the path off."""
+    N, bound = 512, 2**29 - 256
+    rng = np.random.default_rng(41)
+    q = (bound - 2000) // (N - 1)
+    mag = q - rng.integers(0, 4, size=(N, N))
+    Q = np.triu(mag * rng.choice([-1, 1], size=(N, N)), 1).astype(np.int64)
+    W = np.abs(Q + Q.T)
+    b = rng.integers(-900, 901, size=N)
+    b[0] = bound - W[0].sum() + (1 if over else 0)
+    Q[np.arange(N), np.arange(N)] = b
+    hb = (W.sum(axis=1) + np.abs(b)).max()
+    assert hb == bound + (1 if over else 0)
+    Q = Q.astype(np.int32)
+    T_hi, T_lo, inc = 2.2e7, 1.0e5, 2**28
+    R, S, L = 4, 800, 8
+    ctx = api.da_create(Q, 4)
+    sch = api.schedule(T_hi, T_lo, "geometric", L, eoff_inc=inc, init=1)
+    gpu = api.da_anneal_ex(ctx, sch, 0, R, S, 5, api.launch(4, 1, 0, 1, 1), trace=True)
+    assert api.da_last_kernel_stats(ctx)["draw_estimates"] == (0 if over else 1)
+    ref = oracle.anneal(Q, T_hi=T_hi, T_lo=T_lo, n_levels=L, eoff_inc=inc, init=1,
+                        replicas=R, steps=S, seed=5, trace=True)
     _same(gpu, ref, ("trace_k", "trace_E", "trace_eoff") + KEYS)
 
 

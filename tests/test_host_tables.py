@@ -6,7 +6,10 @@ and reject-all entry fit the LDS staging area where the kernel looks for them;
 the band-test form, the one-bracket-read form and the direct-table form of the
 acceptance test each equal d <= thr[u] (the Metropolis test of Algorithm 2 on
 the 16-bit draw) for costs across the band, beyond it and at the ends of the int32
-range; the autotuner's timing window stays inside its schedule; and the host
+range; so does the per-draw estimate form (sign of d - glo + G(u) - 1, exact
+entry only inside the measured window, G of the device's fp32 form with the
+host's log2 in place of the device's), whose int32 sums never wrap for fields
+up to the bound the host allows and offsets up to 2^30; the autotuner's timing window stays inside its schedule; and the host
 guard of every step-kernel launch (job_range_error) passes every step range
 inside a schedule and rejects ranges reaching step S or beyond, negative or
 reversed ranges, offset increments above 2^30 and oversized shapes.  Planting
