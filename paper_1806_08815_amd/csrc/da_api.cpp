@@ -179,9 +179,14 @@ LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch,
     // per-draw estimates: random-number waves, a multi-wave replica reading W
     // from global memory (the wide variants), 4 or 8 flips per lane, and fields
     // small enough for the estimate path's int32 sums; not with direct tables
+    // Left to choose (no tuner), estimates only where fields span many coupling
+    // units: a cost then rarely falls inside an estimate's window of a few
+    // units, while +-1-like instances meet it every step or two.
     const int want_gen = launch ? launch->draw_estimates : 0;
     const bool wide16 = ctx->dtype != 2 || (ctx->wscale < (1 << 15) && ctx->wscale > -(1 << 15));
-    if (want_gen >= 0 && anneal_mode && !sparse && !sh.direct && !sh.w_lds && sh.NH > 0 &&
+    const bool fine_fields = ctx->hbound >= 4096 * (int64_t)std::abs(ctx->wscale);
+    if ((want_gen > 0 || (want_gen == 0 && fine_fields)) && anneal_mode && !sparse &&
+        !sh.direct && !sh.w_lds && sh.NH > 0 &&
         sh.NW > 1 && sh.F >= 4 && wide16 && ctx->hbound <= kGenFieldMax) {
         const size_t lg = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0, stage, sh.NH, false, false, true);
         if (lg <= limit) {

@@ -134,6 +134,21 @@ __device__ __forceinline__ void wave_prefix(int c, int &excl, int &total) {
     }
 }
 
+// The same from a DPP scan: inclusive sums within rows of 16 lanes (shifts 1,
+// 2, 4, 8), then each row's predecessors added by the row broadcasts of lanes
+// 15 and 31; six dependent adds instead of a ballot and two mbcnt per bit.
+__device__ __forceinline__ void wave_scan(int c, int &excl, int &total) {
+    int v = c;
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15 -> rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31 -> rows 2, 3
+    excl = v - c;
+    total = __builtin_amdgcn_readlane(v, 63);
+}
+
 // Position of the r-th (0-based) set bit of a 4-bit mask m, for every (m, r):
 // entry 4 (m & 7) + r of half m >> 3, two bits each.
 constexpr uint64_t select4_half(int half) {
@@ -645,7 +660,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 }
             }
             c = __popc(acc);
-            wave_prefix<CountBits<F>::value>(c, excl, wtot);
+            wave_scan(c, excl, wtot);
             if (NW > 1) rec[par * RS + g] = acc | (xb << 8) | ((uint32_t)(excl + c) << 16);
         } else if (fast) {
             // 1-3a, narrow band with the decisions' table entries already read:
