@@ -37,9 +37,11 @@ namespace dapt {
 // a narrow band, as thr >= -1; stated so that tmin + 1 + E_off + q fits int32).
 //
 // Wide bands can also be decided from a per-draw estimate computed by the
-// random-number waves (kernel variant kModeGen): G(u) = trunc(fma(log2(u + 1/2),
-// ga, gb)) in fp32 with ga = T ln 2 and gb = -16 T ln 2, so that -G(u) is within
-// a few units of thr[u].  A device pass over all 65536 draws measures, with the
+// random-number waves (kernel variant kModeGen): G(u) = bits(fma(log2(u + 1/2),
+// ga, gb)) - kGenMagic in fp32 with ga = T ln 2 and gb = 1.5 2^23 - 16 T ln 2:
+// the sum lands in [2^23, 2^24), where the float's bits minus those of 1.5 2^23
+// are the rounded integer, so -G(u) is within a few units of thr[u] (levels with
+// tmax < 2^22 only).  A device pass over all 65536 draws measures, with the
 // kernel's own instructions, off(u) = thr[u] + G(u) and keeps its range
 // [glo, ghi], so thr[u] lies in [glo - G(u), ghi - G(u)] for every draw:
 // d <= glo - G(u) accepts, d > ghi - G(u) rejects, and only the rare d in
@@ -58,9 +60,11 @@ struct LevelHdr {
 };
 constexpr int kGenWindow = 64;      // widest measured window a level may use
 constexpr int kGenOffMax = 64;      // and |glo|, |ghi| at most this
-// the estimate path keeps d - glo + G(u) - 1 in int32 when |h| stays below
-// this bound and tmax < 2^29
-constexpr int64_t kGenFieldMax = (int64_t(1) << 29) - 256;
+constexpr int32_t kGenTmax = 1 << 22;            // levels with tmax below this only
+constexpr uint32_t kGenMagic = 0x4B400000u;      // bits of 1.5 2^23
+// the estimate path's d - glo + G(u) - 1 stays in int32 when |h| stays below
+// this bound (E_off <= 2^30, tmax < 2^22)
+constexpr int64_t kGenFieldMax = (int64_t(1) << 30) - (int64_t(1) << 22) - 256;
 constexpr int kDirectSpan = 255;
 constexpr int kDirectTmin = 256;
 constexpr int kMaxDirectLevels = 512;   // schedules with more levels use brackets only

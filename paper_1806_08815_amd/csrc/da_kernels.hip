@@ -92,16 +92,18 @@ __device__ __forceinline__ uint32_t philox_x_uniform(uint32_t c0, uint32_t c1, u
     return c0;
 }
 
-// Per-draw estimate G(u) ~ -thr[u] of a level (coefficients ga = T ln 2,
-// gb = -16 T ln 2): -T ln((u + 1/2) / 65536) evaluated as an fp32 base-2
-// logarithm and one fused multiply-add, truncated.  Any deterministic
-// function would do: the window pass below measures thr[u] + G(u) over every
-// draw with these same instructions, and decisions only use G inside that
-// measured bracket.
+// Per-draw estimate of a level (coefficients ga = T ln 2, gb = 1.5 2^23 -
+// 16 T ln 2): T ln((u + 1/2) / 65536) + 1.5 2^23 evaluated as an fp32 base-2
+// logarithm and one fused multiply-add, returned as the float's bits.  For
+// tmax < 2^22 the sum lies in [2^23, 2^24), so the bits are kGenMagic plus the
+// rounded value: G(u) = draw_estimate - kGenMagic ~ -thr[u], with the offset
+// folded into the step's constants.  Any deterministic function would do: the
+// window pass below measures thr[u] + G(u) over every draw with these same
+// instructions, and decisions only use G inside that measured bracket.
 __device__ __forceinline__ int draw_estimate(uint32_t u, float ga, float gb) {
     const float x = (float)u + 0.5f;                 // exact for u < 2^16
     const float lg = __builtin_amdgcn_logf(x);       // v_log_f32
-    return (int)__builtin_fmaf(lg, ga, gb);
+    return __float_as_int(__builtin_fmaf(lg, ga, gb));
 }
 
 __device__ __forceinline__ uint32_t word_of(const uint4 &v, int w) {
@@ -627,17 +629,25 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             // [glo - G, ghi - G], so with z = d - glo + G - 1 (d = (1 - 2x) h -
             // E_off) a flip is accepted when z < 0, rejected when z >= ghi - glo,
             // and only in between is thr[u] read.  The host allows this path
-            // only for |h| <= kGenFieldMax and levels with tmax < 2^29 and
-            // |glo|, |ghi| <= kGenOffMax, so z stays in int32.  The sign bits of
-            // z shift straight into the accepted mask.
-            const int Ec = eoff + hd.glo + 1;
+            // only for |h| <= kGenFieldMax and levels with tmax < 2^22 and
+            // |glo|, |ghi| <= kGenOffMax, so z is in int32; the ring holds
+            // G + kGenMagic, so the sum wraps through 2^32 on the way (unsigned
+            // arithmetic) and lands on z.  The sign bits of z shift straight
+            // into the accepted mask.
+            const uint32_t negEc = (uint32_t)__builtin_amdgcn_readfirstlane(
+                (int)(0u - ((uint32_t)(eoff + hd.glo + 1) + kGenMagic)));
             const uint32_t Wt = (uint32_t)(hd.ghi - hd.glo);
             uint32_t zmin = 0xFFFFFFFFu;
             int zv[F];
 #pragma unroll
             for (int f = F - 1; f >= 0; --f) {
-                const int mx = -(int)((xb >> f) & 1u);
-                const int z = ((h[f] ^ mx) - mx) + tv[f] - Ec;
+                // z = ((h ^ mx) - mx) + G' - Ec with mx = -x: xor, one
+                // three-input add with the step constant, and the sign fix
+                const int mx = __builtin_amdgcn_sbfe((int)xb, f, 1);
+                const uint32_t hx = (uint32_t)(h[f] ^ mx);
+                uint32_t zs;
+                asm("v_add3_u32 %0, %1, %2, %3" : "=v"(zs) : "v"(hx), "v"(tv[f]), "s"(negEc));
+                const int z = (int)(zs - (uint32_t)mx);
                 zv[f] = z;
                 acc = __builtin_amdgcn_alignbit(acc, (uint32_t)z, 31);
                 zmin = min(zmin, (uint32_t)z);
@@ -1446,7 +1456,8 @@ __global__ __launch_bounds__(256) void k_gen_calibrate(LevelHdr *hdr, const int3
     const int32_t *t = thr + (size_t)l * 65536;
     int lo = INT32_MAX, hi = INT32_MIN;
     for (int u = threadIdx.x; u < 65536; u += blockDim.x) {
-        const int off = t[u] + draw_estimate((uint32_t)u, hd.ga, hd.gb);
+        const int off =
+            t[u] + (int)((uint32_t)draw_estimate((uint32_t)u, hd.ga, hd.gb) - kGenMagic);
         lo = min(lo, off);
         hi = max(hi, off);
     }

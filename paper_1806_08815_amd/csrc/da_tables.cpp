@@ -154,10 +154,10 @@ void build_host_tables(const std::vector<double> &temps, HostTables &ht) {
         // candidates for the per-draw estimate: -G(u) ~ T ln(65536 / (u + 1/2));
         // the device measures the window (launch_gen_calibrate)
         const double T = temps[l];
-        if (T > 0.0 && std::isfinite(T) && hd.tmax < (1 << 29)) {
+        if (T > 0.0 && std::isfinite(T) && hd.tmax < kGenTmax) {
             hd.gth = 1;
             hd.ga = (float)(T * std::log(2.0));
-            hd.gb = (float)(-16.0 * T * std::log(2.0));
+            hd.gb = (float)(1.5 * 8388608.0 - 16.0 * T * std::log(2.0));
         }
     }
     if (ht.brk.empty()) ht.brk.push_back(0);

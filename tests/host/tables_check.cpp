@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <cstring>
 #include <random>
 #include <vector>
 
@@ -60,22 +61,30 @@ static bool one_read_form(const int32_t *thr, const LevelHdr &hd, const uint32_t
     return acc;
 }
 
-// The per-draw estimate path (kModeGen) with an estimate G of the device's
-// form evaluated on the host (the host's log2f stands in for v_log_f32; the
-// window is measured over all draws either way): with z = s + G(u) - (E_off +
-// glo + 1) in wrapping int32 arithmetic, z < 0 accepts, ghi - glo <= z rejects,
-// and in between the exact entry decides.  Also checks that z never wraps for
-// |s| <= kGenFieldMax, E_off in [0, 2^30] and tmax < 2^29.
-static int host_estimate(uint32_t u, float ga, float gb) {
+// The per-draw estimate path (kModeGen) with an estimate of the device's form
+// evaluated on the host (the host's log2f stands in for v_log_f32; the window
+// is measured over all draws either way): the ring value is the fp32 sum's
+// bits, G = bits - kGenMagic; with z = s + bits - (E_off + glo + 1 + kGenMagic)
+// in wrapping 32-bit arithmetic, z < 0 accepts, ghi - glo <= z rejects, and in
+// between the exact entry decides.  Also checks that the sum lands in
+// [2^23, 2^24) (so the bits are the rounded value) and that the true z fits
+// int32 for |s| <= kGenFieldMax, E_off in [0, 2^30] and tmax < 2^22.
+static int32_t host_estimate_bits(uint32_t u, float ga, float gb) {
     const float x = (float)u + 0.5f;
-    return (int)std::fma(std::log2(x), ga, gb);
+    const float v = std::fma(std::log2(x), ga, gb);
+    CHECK(v >= 8388608.0f && v < 16777216.0f, "estimate sum %g outside [2^23, 2^24)", (double)v);
+    int32_t b;
+    std::memcpy(&b, &v, 4);
+    return b;
 }
 
-static bool estimate_form(const int32_t *thr, int glo, int ghi, int32_t G, int64_t s, int32_t eoff,
-                          uint32_t u, bool &wrapped) {
-    const int32_t Ec = (int32_t)((uint32_t)eoff + (uint32_t)glo + 1u);
-    const int32_t z = (int32_t)((uint32_t)(int32_t)s + (uint32_t)G - (uint32_t)Ec);
-    wrapped = (int64_t)z != s + (int64_t)G - (int64_t)Ec;
+static bool estimate_form(const int32_t *thr, int glo, int ghi, int32_t bits, int64_t s,
+                          int32_t eoff, uint32_t u, bool &wrapped) {
+    const uint32_t Ec = (uint32_t)eoff + (uint32_t)glo + 1u + kGenMagic;
+    const int32_t z = (int32_t)((uint32_t)(int32_t)s + (uint32_t)bits - Ec);
+    const int64_t G = (int64_t)bits - (int64_t)kGenMagic;
+    const int64_t zt = s + G - ((int64_t)eoff + glo + 1);
+    wrapped = zt < INT32_MIN || zt > INT32_MAX || (int64_t)z != zt;
     if (z < 0) return true;
     if ((uint32_t)z >= (uint32_t)(ghi - glo)) return false;
     return s - eoff <= thr[u];
@@ -143,15 +152,16 @@ int main() {
                 }
             // the estimate path: candidates are exactly the levels with T > 0
             // and tmax < 2^29; window measured over every draw
-            CHECK(hd.gth == ((t[l] > 0.0 && hd.tmax < (1 << 29)) ? 1 : 0), "T=%g: estimate flag",
+            CHECK(hd.gth == ((t[l] > 0.0 && hd.tmax < kGenTmax) ? 1 : 0), "T=%g: estimate flag",
                   t[l]);
             if (!hd.gth) continue;
             int glo = INT32_MAX, ghi = INT32_MIN;
             std::vector<int32_t> G(65536);
             for (uint32_t u = 0; u < 65536; ++u) {
-                G[u] = host_estimate(u, hd.ga, hd.gb);
-                glo = std::min(glo, thr[u] + G[u]);
-                ghi = std::max(ghi, thr[u] + G[u]);
+                G[u] = host_estimate_bits(u, hd.ga, hd.gb);
+                const int32_t off = thr[u] + (int32_t)((uint32_t)G[u] - kGenMagic);
+                glo = std::min(glo, off);
+                ghi = std::max(ghi, off);
             }
             // the device keeps a level only when its window is narrow (fp32
             // rounding widens it with T: a few units up to T ~ 1e6)

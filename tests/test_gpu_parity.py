@@ -170,11 +170,11 @@ def test_draw_estimate_trace_parity(api, kind, N, dtype, F, rpw, init):
 @pytest.mark.parametrize("over", [False, True])
 def test_draw_estimate_field_bound(api, over):
     """Fields at the estimate path's bound: row 0's |b_0| + sum_j |W_0j| is
-    exactly 2^29 - 256 (one more with over), random starts put fields near it
-    at once, tmax sits just under 2^29 and the offset saturates at 2^30, so
-    d - glo + G(u) - 1 reaches the int32 ends.  Over the bound the host keeps
+    exactly 2^30 - 2^22 - 256 (one more with over), random starts put fields
+    near it at once, tmax sits just under 2^22 and the offset saturates at 2^30,
+    so d - glo + G(u) - 1 reaches the int32 ends.  Over the bound the host keeps
     the path off."""
-    N, bound = 512, 2**29 - 256
+    N, bound = 512, 2**30 - 2**22 - 256
     rng = np.random.default_rng(41)
     q = (bound - 2000) // (N - 1)
     mag = q - rng.integers(0, 4, size=(N, N))
@@ -186,7 +186,7 @@ def test_draw_estimate_field_bound(api, over):
     hb = (W.sum(axis=1) + np.abs(b)).max()
     assert hb == bound + (1 if over else 0)
     Q = Q.astype(np.int32)
-    T_hi, T_lo, inc = 2.2e7, 1.0e5, 2**28
+    T_hi, T_lo, inc = 3.5e5, 1.0e4, 2**28
     R, S, L = 4, 800, 8
     ctx = api.da_create(Q, 4)
     sch = api.schedule(T_hi, T_lo, "geometric", L, eoff_inc=inc, init=1)
