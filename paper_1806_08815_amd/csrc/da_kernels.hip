@@ -437,7 +437,8 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         fast = dq && HELP && direct && full;
         // (only in the variants without direct tables: carried beside the
         // one-compare path, its code slows the narrow-band step)
-        fastb = !dq && HELP && full && !perstep && !single && hd.tmax < (1 << 29);
+        // (waves holding ghost flips mask them out of the result)
+        fastb = !dq && HELP && active && !helper && !perstep && !single && hd.tmax < (1 << 29);
         if (direct) {
             const uint4 *src = reinterpret_cast<const uint4 *>(J.q8 + (size_t)hd.q8 * 65536);
             uint4 *dst = reinterpret_cast<uint4 *>(smem + w_bytes + kMaxBuckets * 4);
@@ -732,6 +733,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 for (int f = 0; f < F; ++f)
                     acc |= (((fine >> f) & 1u) & (uint32_t)(sv[f] - eoff <= t[f])) << f;
             }
+            if (!full) acc &= vmask;   // flips past the last variable are never accepted
             c = __popc(acc);
             wave_prefix<CountBits<F>::value>(c, excl, wtot);
             if (NW > 1) rec[par * RS + g] = acc | (xb << 8) | ((uint32_t)(excl + c) << 16);
