@@ -70,19 +70,21 @@ def measured_traffic(workload: str, launch: dict):
     path = os.path.join(ROOT, "profiles", f"pmc_k_run_{workload}.md")
     try:
         with open(path) as f:
-            line = next(l for l in f if l.startswith("machine-readable:"))
-    except (OSError, StopIteration):
+            recs = [json.loads(l.split(":", 1)[1]) for l in f if l.startswith("machine-readable:")]
+    except OSError:
         return None
-    rec = json.loads(line.split(":", 1)[1])
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, name), "rb") as f:
             h.update(f.read())
-    if rec.get("kernel_source_sha256") != h.hexdigest():
-        return None
-    if any(launch.get(k) != v for k, v in rec["launch"].items()):
-        return None
-    return float(rec["traffic_bytes_per_launch"])
+    # one record per launch shape the counters were taken on
+    for rec in recs:
+        if rec.get("kernel_source_sha256") != h.hexdigest():
+            continue
+        if any(launch.get(k) != v for k, v in rec["launch"].items()):
+            continue
+        return float(rec["traffic_bytes_per_launch"])
+    return None
 
 
 def describe(w):
