@@ -404,6 +404,16 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             if (i0 + f < J.N) vmask |= 1u << f;
         }
     }
+    // estimate path: the x bits once more as bytes 0x00 / 0xFF, four flips per
+    // word, so a flip's sign mask is one sign-extended byte operand (SDWA)
+    constexpr int NXW = (F + 3) / 4;
+    uint32_t xbw[NXW];
+#pragma unroll
+    for (int q = 0; q < NXW; ++q) xbw[q] = 0u;
+    if constexpr (gen) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) xbw[f >> 2] |= ((xb >> f) & 1u) ? (0xFFu << (8 * (f & 3))) : 0u;
+    }
     int64_t E = 0, bE = 0, nacc = 0;
     int32_t eoff = 0;
     if (active && !helper) {
@@ -629,26 +639,29 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             // wide band with per-draw estimates G(u): thr[u] lies in
             // [glo - G, ghi - G], so with z = d - glo + G - 1 (d = (1 - 2x) h -
             // E_off) a flip is accepted when z < 0, rejected when z >= ghi - glo,
-            // and only in between is thr[u] read.  The host allows this path
-            // only for |h| <= kGenFieldMax and levels with tmax < 2^22 and
-            // |glo|, |ghi| <= kGenOffMax, so z is in int32; the ring holds
-            // G + kGenMagic, so the sum wraps through 2^32 on the way (unsigned
-            // arithmetic) and lands on z.  The sign bits of z shift straight
+            // and only in between is thr[u] read.  Taking (1 - 2x) h as h ^ -x
+            // (one's complement, short by one when x = 1) and adding 1 gives
+            // zz in {z, z + 1}: zz < 0 still implies z < 0 and zz > ghi - glo
+            // still implies z >= ghi - glo, so the same tests hold with a window
+            // one wider, at one xor (the sign mask a sign-extended byte operand)
+            // and one three-input add per flip.  The host allows this path only
+            // for |h| <= kGenFieldMax and levels with tmax < 2^22 and |glo|,
+            // |ghi| <= kGenOffMax, so z is in int32; the ring holds G +
+            // kGenMagic, so the sum wraps through 2^32 on the way (unsigned
+            // arithmetic) and lands on zz.  The sign bits of zz shift straight
             // into the accepted mask.
             const uint32_t negEc = (uint32_t)__builtin_amdgcn_readfirstlane(
-                (int)(0u - ((uint32_t)(eoff + hd.glo + 1) + kGenMagic)));
-            const uint32_t Wt = (uint32_t)(hd.ghi - hd.glo);
+                (int)(0u - ((uint32_t)(eoff + hd.glo) + kGenMagic)));
+            const uint32_t Wt = (uint32_t)(hd.ghi - hd.glo) + 1u;
             uint32_t zmin = 0xFFFFFFFFu;
             int zv[F];
 #pragma unroll
             for (int f = F - 1; f >= 0; --f) {
-                // z = ((h ^ mx) - mx) + G' - Ec with mx = -x: xor, one
-                // three-input add with the step constant, and the sign fix
-                const int mx = __builtin_amdgcn_sbfe((int)xb, f, 1);
+                const int mx = (int)(int8_t)(xbw[f >> 2] >> (8 * (f & 3)));   // -x
                 const uint32_t hx = (uint32_t)(h[f] ^ mx);
                 uint32_t zs;
                 asm("v_add3_u32 %0, %1, %2, %3" : "=v"(zs) : "v"(hx), "v"(tv[f]), "s"(negEc));
-                const int z = (int)(zs - (uint32_t)mx);
+                const int z = (int)zs;
                 zv[f] = z;
                 acc = __builtin_amdgcn_alignbit(acc, (uint32_t)z, 31);
                 zmin = min(zmin, (uint32_t)z);
@@ -968,6 +981,11 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 dEs[par] = xk ? -hsel : hsel;   // (1 - 2 x_k) h_k
             }
             xb ^= owner ? (1u << (k % F)) : 0u;
+            if constexpr (gen) {
+                const uint32_t mb = owner ? (0xFFu << (8 * ((k % F) & 3))) : 0u;
+#pragma unroll
+                for (int q = 0; q < NXW; ++q) xbw[q] ^= ((k % F) >> 2) == q ? mb : 0u;
+            }
             if (sparse) {
                 // only k's neighbours change.  Each wave takes the entries of
                 // row k's list that fall in its own columns: one lane per
