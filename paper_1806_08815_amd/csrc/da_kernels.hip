@@ -980,11 +980,18 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 for (int f = 1; f < F; ++f) hsel = (bit == f) ? h[f] : hsel;
                 dEs[par] = xk ? -hsel : hsel;   // (1 - 2 x_k) h_k
             }
-            xb ^= owner ? (1u << (k % F)) : 0u;
             if constexpr (gen) {
-                const uint32_t mb = owner ? (0xFFu << (8 * ((k % F) & 3))) : 0u;
-#pragma unroll
-                for (int q = 0; q < NXW; ++q) xbw[q] ^= ((k % F) >> 2) == q ? mb : 0u;
+                // only the owning lane changes: the other wave skips this
+                // (the flip's byte word chosen by a wave-uniform branch)
+                if (owner) {
+                    const int fb = k % F;
+                    xb ^= 1u << fb;
+                    const uint32_t mb = 0xFFu << (8 * (fb & 3));
+                    if (fb < 4) xbw[0] ^= mb;
+                    else xbw[NXW - 1] ^= mb;
+                }
+            } else {
+                xb ^= owner ? (1u << (k % F)) : 0u;
             }
             if (sparse) {
                 // only k's neighbours change.  Each wave takes the entries of
