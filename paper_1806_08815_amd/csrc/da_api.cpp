@@ -1270,8 +1270,24 @@ int pt_run(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t 
 
     da_schedule sched{temps[0], temps[0], DA_SCHED_GEOMETRIC, 1, eoff_inc, DA_INIT_RANDOM,
                       DA_TRIAL_PARALLEL, 0};
-    const LaunchShape sh = choose_shape(ctx, R, nullptr, false);
+    LaunchShape sh = choose_shape(ctx, R, nullptr, false);
     JobDesc J = make_job(ctx, *lt, R, 0u, seed, 0, sched, sh);
+    // per-draw estimates (one replica per workgroup, several compute waves,
+    // fields of many coupling units, as for anneals; the levels' windows are
+    // measured when the tables are made): handed over by the random-number
+    // waves, whose ring then needs its estimate part in LDS, or evaluated by
+    // the compute lanes themselves
+    const bool wide16 = ctx->dtype != 2 || (ctx->wscale < (1 << 15) && ctx->wscale > -(1 << 15));
+    J.gth = (lt->any_gth && sh.RPW == 1 && sh.NW > 1 && sh.F >= 4 && !sh.w_lds && wide16 &&
+             ctx->ell_D == 0 && ctx->hbound <= kGenFieldMax &&
+             ctx->hbound >= 4096 * (int64_t)std::abs(ctx->wscale))
+                ? 1
+                : 0;
+    if (J.gth && sh.NH > 0) {
+        const size_t lg = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0, 1, sh.NH, false, false, true);
+        if (lg <= (size_t)device_lds_limit()) sh.lds = lg;
+        else J.gth = 0;
+    }
     J.L = M;
     J.lvl_of_rep = ctx->pt_lvl;
     J.round_ptr = ctx->pt_round;
@@ -1318,7 +1334,7 @@ int pt_run(da_ctx *ctx, const double *temps, int32_t M, int32_t chains, int64_t 
     for (; done < rounds && !rc; ++done) rc = check_hip(ctx, (hipError_t)one_round(), "PT round launch");
     if (!rc) rc = check_hip(ctx, hipEventRecord(pe1, s), "event record");
     if (rc) return rc;
-    record_stats(ctx, sh, 1);
+    record_stats(ctx, sh, 1, J.gth);
 
     if (out) {
         da_result o{out->best_x, out->best_E, out->final_x, out->final_E, out->n_accept};

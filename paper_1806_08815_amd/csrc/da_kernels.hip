@@ -358,7 +358,9 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     const uint8_t *q_l = smem + w_bytes + kMaxBuckets * 4;
     // per-draw estimates handed over by the random-number waves (wide bands)
     constexpr bool gen = (MODE & kModeGen) != 0;
-    static_assert(!gen || (HELP && F >= 4 && !BATCH), "estimates come from random-number waves");
+    // (with random-number waves they hand the estimates over; without, each
+    // compute lane draws its block and evaluates them itself)
+    static_assert(!gen || (F >= 4 && !BATCH), "estimates: 4 or 8 flips per lane");
     const SlotLayout SL = slot_layout(NW, NH, sparse ? F : 0, gen);
     uint8_t *sel = smem + w_bytes + (stage ? kMaxBuckets * 4 + (has_q ? 65536 : 0) : 0) +
                    (size_t)SL.bytes * slot;
@@ -653,6 +655,16 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             const uint32_t negEc = (uint32_t)__builtin_amdgcn_readfirstlane(
                 (int)(0u - ((uint32_t)(eoff + hd.glo) + kGenMagic)));
             const uint32_t Wt = (uint32_t)(hd.ghi - hd.glo) + 1u;
+            if constexpr (!HELP) {
+                // no random-number waves: this lane's block of the step, and
+                // its estimates, here
+#pragma unroll
+                for (int q = 0; q < NB; ++q)
+                    rb[q] = philox((uint32_t)(i0 >> 3) + q, (uint32_t)s, rid, kTagMetropolis, k0,
+                                   k1);
+#pragma unroll
+                for (int f = 0; f < F; ++f) tv[f] = draw_estimate(draw16(rb, f), hd.ga, hd.gb);
+            }
             uint32_t zmin = 0xFFFFFFFFu;
             int zv[F];
 #pragma unroll
@@ -670,7 +682,11 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 // a flip inside the window (rare): the exact table entry.  This
                 // step's draws are still in ring slot s & 1.
                 uint4 rt[NB];
-                consume(s, rt);
+                if constexpr (HELP) consume(s, rt);
+                else {
+#pragma unroll
+                    for (int q = 0; q < NB; ++q) rt[q] = rb[q];
+                }
                 const int32_t *thr = J.thr + (size_t)lvl * 65536;
                 int t[F];
 #pragma unroll
@@ -867,7 +883,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         uint4 rbn[NB];
         if (HELP) consume(s + 1, rbn);
         int tvn[F];
-        if (gen) read_est(s + 1, tvn);
+        if (gen && HELP) read_est(s + 1, tvn);
         const uint32_t vs = HELP ? vring[(int)(s & 3)] : 0u;
         int dEp = 0, tw = 0;
         uint32_t r4[4] = {0u, 0u, 0u, 0u};
@@ -885,7 +901,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         } else if (HELP) {
             asm volatile("" ::"v"(vs));
         }
-        if (gen) {
+        if (gen && HELP) {
 #pragma unroll
             for (int f = 0; f < F; ++f) asm volatile("" ::"v"(tvn[f]));
         }
@@ -1055,7 +1071,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
 #pragma unroll
             for (int q = 0; q < NB; ++q) rb[q] = rbn[q];
         }
-        if (gen) {
+        if (gen && HELP) {
 #pragma unroll
             for (int f = 0; f < F; ++f) tv[f] = tvn[f];
         }
@@ -1533,6 +1549,14 @@ int launch_run_t(const JobDesc &J, const TraceDesc &T, int blocks, int threads, 
         // theirs through L1/L2
         if constexpr (!TRACE) {
             if (J.RPW == 1) {
+                if constexpr (F >= 4) {
+                    // per-draw estimates, evaluated by the compute lanes
+                    if (J.gth && wide) {
+                        hipLaunchKernelGGL((k_run<WT, F, false, HELP, true, kModeWide | kModeGen>),
+                                           g, b, lds, S(stream), J, T);
+                        return (int)hipGetLastError();
+                    }
+                }
                 if (wide)
                     hipLaunchKernelGGL((k_run<WT, F, false, HELP, true, kModeWide>), g, b, lds,
                                        S(stream), J, T);
@@ -1651,6 +1675,16 @@ int launch_run_w(const JobDesc &J, int F, bool help, const TraceDesc *trace, int
 int launch_run(const JobDesc &J, int F, bool help, const TraceDesc *trace, int blocks,
                int threads, size_t lds_bytes, void *stream) {
     if (job_range_error(J) != nullptr) return (int)hipErrorInvalidValue;
+    // the workgroup's LDS must hold at least W when staged and every replica
+    // slot in the layout the kernel will use (the estimate ring included)
+    {
+        const SlotLayout SL = slot_layout(J.NW, help ? J.NH : 0, J.ell ? F : 0,
+                                          J.gth != 0 && help);
+        const int64_t w_src = J.ell ? (int64_t)J.N * J.ell_D * 4
+                                    : (int64_t)J.N * J.ld * (int64_t)J.dtype;
+        const int64_t need = (int64_t)SL.bytes * J.RPW + (J.w_lds ? ((w_src + 15) & ~15) : 0);
+        if ((int64_t)lds_bytes < need) return (int)hipErrorInvalidValue;
+    }
     if (J.ell && !J.lvl_of_rep)
         return launch_run_w<int16_t>(J, F, help, trace, blocks, threads, lds_bytes, stream);
     switch (J.dtype) {

@@ -53,6 +53,26 @@ def test_pt_gaussian_parity(api):
         assert np.array_equal(gpu[k], ref[k]), k
 
 
+@pytest.mark.parametrize("chains", [2, 40])
+def test_pt_gaussian_estimates_parity(api, chains):
+    """Gaussian PT takes per-draw estimates: with few replicas the
+    random-number waves hand them over (the estimate ring in LDS), with many
+    (40 chains x 16 temperatures: lazy draws) the compute lanes evaluate them;
+    one sampled chain against the oracle either way."""
+    N, M, K, rounds = 700, 16, 300, 6
+    Q = instances.ising_to_qubo(instances.sk_gaussian(N, 4, scale=2**16))[0]
+    temps = workloads.pt_temperatures(M, 0.1, 3.0, scale=2**16)
+    ctx = api.da_create(Q)
+    gpu = api.da_pt(ctx, temps, chains, rounds, K, 2**16, 11)
+    assert api.da_last_kernel_stats(ctx)["draw_estimates"] == 1
+    c = chains - 1
+    ref = oracle.pt(Q, temps, chains=1, rounds=rounds, steps_per_round=K, eoff_inc=2**16,
+                    seed=11, chain_base=c)
+    rows = slice(c * M, (c + 1) * M)
+    for k in KEYS + ("slot",):
+        assert np.array_equal(gpu[k][rows], ref[k]), k
+
+
 def _sampled(api, name, rows, dtype=None, launch=None):
     w = workloads.WORKLOADS[name]
     Q, _ = w.instance()
