@@ -134,12 +134,13 @@ typedef struct da_trace {
  *                       step's draws one step ahead, off the critical path;
  *                       -1: the compute waves draw lazily, only for undecided
  *                       flips; 0: auto
- *   draw_estimates      with random-number waves, wide bands and at least 4
- *                       flips per lane: 1 lets those waves also hand over an
- *                       fp32 estimate of each draw's threshold, so most flips
- *                       are decided by one compare and only flips inside the
- *                       estimate's measured window read the exact table;
- *                       -1: never; 0: auto */
+ *   draw_estimates      wide bands, several compute waves per replica and at
+ *                       least 4 flips per lane: 1 decides flips against an
+ *                       fp32 estimate of each draw's threshold (handed over by
+ *                       the random-number waves, or evaluated by the compute
+ *                       lanes under lazy draws), so most flips take one sign
+ *                       test and only those inside the estimate's measured
+ *                       window read the exact table; -1: never; 0: auto */
 typedef struct da_launch {
     int32_t flips_per_lane;
     int32_t replicas_per_block;

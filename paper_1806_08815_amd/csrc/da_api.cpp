@@ -176,8 +176,9 @@ LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch,
         sh.direct = 0;
         sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0, stage, sh.NH, sparse);
     }
-    // per-draw estimates: random-number waves, a multi-wave replica reading W
-    // from global memory (the wide variants), 4 or 8 flips per lane, and fields
+    // per-draw estimates (handed over by random-number waves, or evaluated by
+    // the compute lanes under lazy draws): a multi-wave replica reading W from
+    // global memory (the wide variants), 4 or 8 flips per lane, and fields
     // small enough for the estimate path's int32 sums; not with direct tables
     // Left to choose (no tuner), estimates only where fields span many coupling
     // units: a cost then rarely falls inside an estimate's window of a few
@@ -186,8 +187,8 @@ LaunchShape choose_shape(const da_ctx *ctx, int32_t R, const da_launch *launch,
     const bool wide16 = ctx->dtype != 2 || (ctx->wscale < (1 << 15) && ctx->wscale > -(1 << 15));
     const bool fine_fields = ctx->hbound >= 4096 * (int64_t)std::abs(ctx->wscale);
     if ((want_gen > 0 || (want_gen == 0 && fine_fields)) && anneal_mode && !sparse &&
-        !sh.direct && !sh.w_lds && sh.NH > 0 &&
-        sh.NW > 1 && sh.F >= 4 && wide16 && ctx->hbound <= kGenFieldMax) {
+        !sh.direct && !sh.w_lds && sh.NW > 1 && sh.F >= 4 && wide16 &&
+        ctx->hbound <= kGenFieldMax) {
         const size_t lg = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0, stage, sh.NH, false, false, true);
         if (lg <= limit) {
             sh.gen = 1;
@@ -274,6 +275,12 @@ LaunchShape batch_shape(const da_ctx *ctx) {
     sh.w_lds = 0;
     sh.threads = 1024;
     sh.lds = run_lds_bytes(sh.NW, sh.RPW, sh.F, 0, 1, 0, ctx->ell_D > 0);
+    // per-draw estimates evaluated by the compute lanes, as for anneals: fields
+    // of many coupling units within the path's int32 bound, dense rows
+    sh.gen = (ctx->ell_D == 0 && ctx->hbound <= kGenFieldMax &&
+              ctx->hbound >= 4096 * (int64_t)std::abs(ctx->wscale))
+                 ? 1
+                 : 0;
     return sh;
 }
 

@@ -287,7 +287,9 @@ size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk, int
 // replica spans several compute waves, W is read from global memory and
 // 16-bit couplings have a common factor below 2^15, so the single-wave,
 // LDS-resident and 24-bit update paths drop out of the step loop.
-// kModeDirect carries the direct-table decisions of narrow-band levels.
+// kModeDirect carries the direct-table decisions of narrow-band levels;
+// kModeGen the per-draw threshold estimates of wide bands (for jobs that set
+// gth, on levels whose window was measured narrow).
 // BATCH: the persistent batched kernel, whose workgroups may hold more waves
 // than the job's replica slots.
 template <typename WT, int F, bool TRACE, bool HELP, bool STAGE, int MODE, bool BATCH = false>
@@ -360,7 +362,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     constexpr bool gen = (MODE & kModeGen) != 0;
     // (with random-number waves they hand the estimates over; without, each
     // compute lane draws its block and evaluates them itself)
-    static_assert(!gen || (F >= 4 && !BATCH), "estimates: 4 or 8 flips per lane");
+    static_assert(!gen || F >= 4, "estimates: 4 or 8 flips per lane");
     const SlotLayout SL = slot_layout(NW, NH, sparse ? F : 0, gen);
     uint8_t *sel = smem + w_bytes + (stage ? kMaxBuckets * 4 + (has_q ? 65536 : 0) : 0) +
                    (size_t)SL.bytes * slot;
@@ -637,7 +639,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         uint32_t acc = 0;
         int c = 0, excl = 0, wtot = 0;
 
-        if (gen && hd.gth && full) {
+        if (gen && J.gth && hd.gth && full) {
             // wide band with per-draw estimates G(u): thr[u] lies in
             // [glo - G, ghi - G], so with z = d - glo + G - 1 (d = (1 - 2x) h -
             // E_off) a flip is accepted when z < 0, rejected when z >= ghi - glo,
@@ -1606,7 +1608,7 @@ int launch_run_t(const JobDesc &J, const TraceDesc &T, int blocks, int threads, 
     }
     switch (mode) {
         case kModePlain:
-            if constexpr (HELP && F >= 4) {
+            if constexpr (F >= 4) {
                 if (J.gth && wide && !J.q8) {
                     hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, kModeWide | kModeGen>), g,
                                        b, lds, S(stream), J, T);
@@ -1702,8 +1704,8 @@ int launch_batch(const JobDesc *jobs_dev, const BatchItem *items_dev, const int3
         hipLaunchKernelGGL((k_batch<8, kModeDynamic>), dim3(blocks), dim3(threads), lds_bytes,
                            S(stream), jobs_dev, items_dev, n_items_dev, counter_dev);
     else
-        hipLaunchKernelGGL((k_batch<8, kModePlain>), dim3(blocks), dim3(threads), lds_bytes,
-                           S(stream), jobs_dev, items_dev, n_items_dev, counter_dev);
+        hipLaunchKernelGGL((k_batch<8, kModePlain | kModeGen>), dim3(blocks), dim3(threads),
+                           lds_bytes, S(stream), jobs_dev, items_dev, n_items_dev, counter_dev);
     return (int)hipGetLastError();
 }
 

@@ -144,10 +144,12 @@ def test_wide_band_trace_parity(api, N, dtype, F, rpw):
     ("gauss", 4096, 2, 8, 1, 1), ("sk", 1024, 0, 8, 1, 0), ("sk", 1000, 1, 4, 2, 1),
     ("sk", 300, 0, 4, 4, 0), ("random", 777, 0, 4, 1, 1),
 ])
-def test_draw_estimate_trace_parity(api, kind, N, dtype, F, rpw, init):
-    """Per-draw estimates: the random-number waves hand over G(u) ~ -thr[u] and
-    full waves decide each flip by the sign of d - glo + G(u) - 1, reading
-    thr[u] only inside the measured window.  Gaussian levels are wide; the
+@pytest.mark.parametrize("rng", [1, -1])
+def test_draw_estimate_trace_parity(api, kind, N, dtype, F, rpw, init, rng):
+    """Per-draw estimates: the random-number waves hand over G(u) ~ -thr[u]
+    (rng = 1; with rng = -1 each compute lane draws its block and evaluates
+    them itself) and full waves decide each flip by the sign of
+    d - glo + G(u) - 1, reading thr[u] only inside the measured window.  Gaussian levels are wide; the
     +-1 and small-integer instances have levels of a few units, so costs sit
     inside the window often and the exact reads run many times per step.
     Short levels keep the direct tables off, so every level takes the
@@ -160,8 +162,9 @@ def test_draw_estimate_trace_parity(api, kind, N, dtype, F, rpw, init):
     R, S, L = 4, 1500, 12   # levels of 125 steps: no direct tables
     ctx = api.da_create(Q, dtype)
     sch = api.schedule(T_hi, T_lo, "geometric", L, eoff_inc=inc, init=init)
-    gpu = api.da_anneal_ex(ctx, sch, 2, R, S, 29, api.launch(F, rpw, 0, 1, 1), trace=True)
-    assert api.da_last_kernel_stats(ctx)["draw_estimates"] == 1
+    gpu = api.da_anneal_ex(ctx, sch, 2, R, S, 29, api.launch(F, rpw, 0, rng, 1), trace=True)
+    st = api.da_last_kernel_stats(ctx)
+    assert st["draw_estimates"] == 1 and (st["rng_waves"] > 0) == (rng > 0)
     ref = oracle.anneal(Q, T_hi=T_hi, T_lo=T_lo, n_levels=L, eoff_inc=inc, init=init,
                         replica_base=2, replicas=R, steps=S, seed=29, trace=True)
     _same(gpu, ref, ("trace_k", "trace_E", "trace_eoff") + KEYS)
