@@ -218,8 +218,10 @@ __host__ __device__ inline SlotLayout slot_layout(int NW, int NH, int dhF = 0, b
         off += 8;
     }
     if (NH > 0) {
+        // selection draws of 128 steps: the random-number waves write 64 at a
+        // time, one step per lane
         L.vring = off;
-        off += 16;
+        off += 128 * 4;
         off = (off + 15) & ~15;
         L.draws = off;
         off += 2 * NH * 64 * 16;

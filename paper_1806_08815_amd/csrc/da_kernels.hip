@@ -370,7 +370,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     const int RS = max(NW, 4) * 64;
     uint32_t *rec = reinterpret_cast<uint32_t *>(sel + SL.rec);    // [2][RS]
     int *dEs = reinterpret_cast<int *>(sel + SL.dEs);              // [2]
-    uint32_t *vring = reinterpret_cast<uint32_t *>(sel + SL.vring);  // [4] selection draws
+    uint32_t *vring = reinterpret_cast<uint32_t *>(sel + SL.vring);  // [128] selection draws
     uint4 *draws = reinterpret_cast<uint4 *>(sel + SL.draws);      // [2][NH*64] Philox blocks
     int4 *est = reinterpret_cast<int4 *>(sel + SL.est);            // [2][2][NH*64] estimates
     // sparse rows: this wave's field-delta buffer [64 * F], kept all zero between steps
@@ -519,9 +519,14 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 dst[NH * 64 + b] = e1;
             }
         }
-        if (active && wr == NH - 1) {
-            const uint32_t v = philox_x_uniform(0u, (uint32_t)st, rid, kTagSelect, k0, k1);
-            if (lane == 0) vring[(int)(st & 3)] = v;
+        // selection draws 64 steps at a time, one step per lane, at the first
+        // step of every aligned run of 64 (and at the launch's first step): the
+        // ring holds 128, so the run being written never meets the step being
+        // read
+        if (active && wr == NH - 1 && ((st & 63) == 0 || st == s0)) {
+            const int64_t sl = (st & ~(int64_t)63) + lane;
+            const uint32_t v = philox(0u, (uint32_t)sl, rid, kTagSelect, k0, k1).x;
+            vring[(int)(sl & 127)] = v;
         }
     };
     // compute waves: this lane's draws of step st (written by the generators)
@@ -886,7 +891,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         if (HELP) consume(s + 1, rbn);
         int tvn[F];
         if (gen && HELP) read_est(s + 1, tvn);
-        const uint32_t vs = HELP ? vring[(int)(s & 3)] : 0u;
+        const uint32_t vs = HELP ? vring[(int)(s & 127)] : 0u;
         int dEp = 0, tw = 0;
         uint32_t r4[4] = {0u, 0u, 0u, 0u};
         if (NW > 1) {
