@@ -186,6 +186,26 @@ __device__ __forceinline__ int select_bit(uint32_t m, int r) {
     return r < c ? select_bit4(low, r) : 4 + select_bit4(m >> 4, r - c);
 }
 
+// h[bit] for a wave-uniform bit: a select tree on the bits of `bit` (F - 1
+// selects, log2 F uniform conditions)
+// (explicit selects: written as plain conditionals the compiler turns the
+// tree back into an indexed read, a compare chain per level)
+template <int F>
+__device__ __forceinline__ int pick_field(const int (&h)[F], int bit) {
+    const int ub = __builtin_amdgcn_readfirstlane(bit);
+    int v[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) v[f] = h[f];
+#pragma unroll
+    for (int w = 1; w < F; w <<= 1) {
+        const uint64_t up = (ub & w) ? ~0ull : 0ull;   // wave-uniform lane mask
+#pragma unroll
+        for (int q = 0; q < F; q += 2 * w)
+            asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(v[q]) : "v"(v[q]), "v"(v[q + w]), "s"(up));
+    }
+    return v[0];
+}
+
 template <int F>
 struct CountBits {
     static constexpr int value = F >= 8 ? 4 : (F >= 4 ? 3 : (F >= 2 ? 2 : 1));
@@ -302,6 +322,8 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     constexpr int NB = (F + 7) / 8;   // Philox blocks per lane
     typedef typename VecOf<WT, F>::type RowV;
     const int lane = threadIdx.x & 63;
+    // lanes 0..F-1: the flips at or above position `lane` of a lane's mask
+    const uint32_t ge_mask = lane < F ? ((0xFFu << lane) & ((1u << F) - 1u)) : 0u;
     // wave-level quantities are uniform: keep them in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     constexpr bool wide = (MODE & kModeWide) != 0;
@@ -530,9 +552,10 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         }
     };
     // compute waves: this lane's draws of step st (written by the generators)
-    auto consume = [&](int64_t st, uint4 (&dst)[NB]) {
+    // (o: element offset of the ring slot, (st & 1) * NH * 64 for step st)
+    auto consume_at = [&](int o, uint4 (&dst)[NB]) {
         // lanes past the last variable only hold ghost flips: clamp their reads
-        const uint4 *src = draws + (int)(st & 1) * NH * 64;
+        const uint4 *src = draws + o;
         if (F >= 8) {
 #pragma unroll
             for (int q = 0; q < NB; ++q) dst[q] = src[min((i0 >> 3) + q, NH * 64 - 1)];
@@ -547,9 +570,12 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         }
     };
 
-    // compute waves: this lane's per-draw estimates of step st
-    auto read_est = [&](int64_t st, int (&dst)[F]) {
-        const int4 *src = est + (int)(st & 1) * 2 * NH * 64;
+    auto consume = [&](int64_t st, uint4 (&dst)[NB]) { consume_at((int)(st & 1) * NH * 64, dst); };
+
+    // compute waves: this lane's per-draw estimates of a step (o: element
+    // offset of its ring slot, (st & 1) * 2 * NH * 64 for step st)
+    auto read_est_at = [&](int o, int (&dst)[F]) {
+        const int4 *src = est + o;
         if constexpr (!gen) {
             (void)src;
         } else if constexpr (F >= 8) {
@@ -563,6 +589,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             dst[0] = a.x; dst[1] = a.y; dst[2] = a.z; dst[3] = a.w;
         }
     };
+    auto read_est = [&](int64_t st, int (&dst)[F]) { read_est_at((int)(st & 1) * 2 * NH * 64, dst); };
 
     uint4 rb[NB];
     int tv[F];   // this step's per-draw estimates (kModeGen)
@@ -618,13 +645,35 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             __syncthreads();
         }
     }
+    // estimate path of the level in force, in scalar registers (set when a
+    // level opens): whether this wave takes it, the window width and the step
+    // constant without the offset
+    bool gpath = false;
+    uint32_t gWt = 0u, gC = 0u;
+    auto gen_level = [&]() {
+        if constexpr (gen) {
+            gpath = J.gth && full && __builtin_amdgcn_readfirstlane(hd.gth) != 0;
+            const int glo = __builtin_amdgcn_readfirstlane(hd.glo);
+            const int ghi = __builtin_amdgcn_readfirstlane(hd.ghi);
+            gWt = (uint32_t)(ghi - glo) + 1u;
+            gC = 0u - ((uint32_t)glo + kGenMagic);
+        }
+    };
+    gen_level();
+    // LDS slots by step parity, toggled every step: this step's lane records
+    // and the next step's draws and estimates (element offsets)
+    int rec_o = (int)(s0 & 1) * RS;
+    int drw_o = (int)((s0 + 1) & 1) * NH * 64;
+    int est_o = (int)((s0 + 1) & 1) * 2 * NH * 64;
     for (int64_t left = (HELP && helper) ? 0 : (s1 > s0 ? s1 - s0 : 0); left != 0;
-         --left, ++s, --to_next) {
+         --left, ++s, --to_next, rec_o = RS - rec_o, drw_o = NH * 64 - drw_o,
+                 est_o = 2 * NH * 64 - est_o) {
         if (to_next == 0) {
             lvl = level_of(s, J.L, J.S);
             s_next = next_level_step(lvl, J.L, J.S);
             to_next = s_next - s;
             hd = J.hdr[lvl];
+            gen_level();
             if (stage) {
                 stage_brackets();
                 if (HELP && direct) lookup_q(rb, qv);
@@ -644,7 +693,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         uint32_t acc = 0;
         int c = 0, excl = 0, wtot = 0;
 
-        if (gen && J.gth && hd.gth && full) {
+        if (gen && gpath) {
             // wide band with per-draw estimates G(u): thr[u] lies in
             // [glo - G, ghi - G], so with z = d - glo + G - 1 (d = (1 - 2x) h -
             // E_off) a flip is accepted when z < 0, rejected when z >= ghi - glo,
@@ -659,9 +708,8 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             // kGenMagic, so the sum wraps through 2^32 on the way (unsigned
             // arithmetic) and lands on zz.  The sign bits of zz shift straight
             // into the accepted mask.
-            const uint32_t negEc = (uint32_t)__builtin_amdgcn_readfirstlane(
-                (int)(0u - ((uint32_t)(eoff + hd.glo) + kGenMagic)));
-            const uint32_t Wt = (uint32_t)(hd.ghi - hd.glo) + 1u;
+            const uint32_t negEc = gC - (uint32_t)eoff;
+            const uint32_t Wt = gWt;
             if constexpr (!HELP) {
                 // no random-number waves: this lane's block of the step, and
                 // its estimates, here
@@ -679,7 +727,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 const int mx = (int)(int8_t)(xbw[f >> 2] >> (8 * (f & 3)));   // -x
                 const uint32_t hx = (uint32_t)(h[f] ^ mx);
                 uint32_t zs;
-                asm("v_add3_u32 %0, %1, %2, %3" : "=v"(zs) : "v"(hx), "v"(tv[f]), "s"(negEc));
+                asm("v_add3_u32 %0, %1, %2, %3" : "=v"(zs) : "v"(hx), "v"(tv[f]), "v"(negEc));
                 const int z = (int)zs;
                 zv[f] = z;
                 acc = __builtin_amdgcn_alignbit(acc, (uint32_t)z, 31);
@@ -708,7 +756,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             }
             c = __popc(acc);
             wave_scan(c, excl, wtot);
-            if (NW > 1) rec[par * RS + g] = acc | (xb << 8) | ((uint32_t)(excl + c) << 16);
+            if (NW > 1) rec[rec_o + g] = acc | (xb << 8) | ((uint32_t)(excl + c) << 16);
         } else if (fast) {
             // 1-3a, narrow band with the decisions' table entries already read:
             // with s = (1 - 2x) h the flip is accepted iff s - E_off <= thr[u]
@@ -731,7 +779,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 wtot += (int)__popcll(pm);
             }
             c = __popc(acc);
-            if (NW > 1) rec[par * RS + g] = acc | (xb << 8) | ((uint32_t)(excl + c) << 16);
+            if (NW > 1) rec[rec_o + g] = acc | (xb << 8) | ((uint32_t)(excl + c) << 16);
         } else if (fastb) {
             // wide band with the draws at hand: one bracket read per flip and
             // no band tests.  With s = (1 - 2x) h and C = tmin + 1 + E_off,
@@ -772,7 +820,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             if (!full) acc &= vmask;   // flips past the last variable are never accepted
             c = __popc(acc);
             wave_prefix<CountBits<F>::value>(c, excl, wtot);
-            if (NW > 1) rec[par * RS + g] = acc | (xb << 8) | ((uint32_t)(excl + c) << 16);
+            if (NW > 1) rec[rec_o + g] = acc | (xb << 8) | ((uint32_t)(excl + c) << 16);
         } else if (!idle) {
             // 1. cost of every flip and the draw-free decisions (branch-free).
             // Without direct tables the band tmin < d <= tmax is tested as one
@@ -878,7 +926,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             c = __popc(acc);
             wave_prefix<CountBits<F>::value>(c, excl, wtot);
             // record: accepted mask | x bits << 8 | inclusive prefix << 16
-            if (NW > 1) rec[par * RS + g] = acc | (xb << 8) | ((uint32_t)(excl + c) << 16);
+            if (NW > 1) rec[rec_o + g] = acc | (xb << 8) | ((uint32_t)(excl + c) << 16);
         }
         if (sync) __syncthreads();
         if (idle) continue;
@@ -888,17 +936,17 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         // wave waits for LDS once.
         // (on the last step these read draws no step uses: stale, in bounds)
         uint4 rbn[NB];
-        if (HELP) consume(s + 1, rbn);
+        if (HELP) consume_at(drw_o, rbn);
         int tvn[F];
-        if (gen && HELP) read_est(s + 1, tvn);
+        if (gen && HELP) read_est_at(est_o, tvn);
         const uint32_t vs = HELP ? vring[(int)(s & 127)] : 0u;
         int dEp = 0, tw = 0;
         uint32_t r4[4] = {0u, 0u, 0u, 0u};
         if (NW > 1) {
             dEp = dEs[par ^ 1];
-            const int twr = (int)(rec[par * RS + min(lane, NW - 1) * 64 + 63] >> 16);
+            const int twr = (int)(rec[rec_o + min(lane, NW - 1) * 64 + 63] >> 16);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) r4[q] = rec[par * RS + q * 64 + lane];
+            for (int q = 0; q < 4; ++q) r4[q] = rec[rec_o + q * 64 + lane];
             tw = lane < NW ? twr : 0;
             // keep these reads together: left to itself the compiler sinks
             // the draw and record reads into the branches that use them, so
@@ -913,6 +961,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             for (int f = 0; f < F; ++f) asm volatile("" ::"v"(tvn[f]));
         }
         int m, k = 0, xk = 0, dk = 0, bit = 0;
+        int kw = 0, kl = 0;   // wave and lane holding the chosen flip
         if (NW == 1) {
             m = wtot;
             if (m > 0) {
@@ -924,6 +973,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 const int rloc = j - readlane(excl, ts);
                 const uint32_t msk = (uint32_t)readlane((int)acc, ts);
                 bit = select_bit<F>(msk, rloc);
+                kl = ts;
                 k = ts * F + bit;
                 xk = (readlane((int)xb, ts) >> bit) & 1;
                 // energy change (1 - 2 x_k) h_k of the chosen flip
@@ -957,14 +1007,20 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                     const uint32_t r23 = (ws & 1) ? r4[3] : r4[2];
                     r2 = (ws & 2) ? r23 : r01;
                 } else {
-                    r2 = rec[par * RS + ws * 64 + lane];
+                    r2 = rec[rec_o + ws * 64 + lane];
                 }
                 // first lane of wave ws whose inclusive prefix passes jw
                 const uint64_t bal = ballot((int)(r2 >> 16) > jw);
                 const int ts = (int)__builtin_ctzll(bal);
                 const uint32_t rs = (uint32_t)readlane((int)r2, ts);
-                const int rloc = jw - ((int)(rs >> 16) - __popc(rs & 0xFFu));
-                bit = select_bit<F>(rs & 0xFFu, rloc);
+                // the flip: the set bit of the lane's mask with incl - jw set
+                // bits at or above it (incl its inclusive prefix; 1 <= incl -
+                // jw <= its count), found by lanes 0..F-1 at once
+                const uint32_t need = (rs >> 16) - (uint32_t)jw;
+                const uint64_t hit = ballot((uint32_t)__popc(rs & ge_mask) == need);
+                bit = (int)__builtin_ctz((uint32_t)hit & rs);
+                kw = ws;
+                kl = ts;
                 k = (ws * 64 + ts) * F + bit;
                 xk = (rs >> (8 + bit)) & 1;
             }
@@ -996,25 +1052,20 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         if (m > 0) {
             // apply the flip: state, energy, every field
             const int delta = xk ? -1 : 1;
-            const bool owner = g == (k / F);
-            if (NW > 1 && owner) {
-                int hsel = h[0];
-#pragma unroll
-                for (int f = 1; f < F; ++f) hsel = (bit == f) ? h[f] : hsel;
-                dEs[par] = xk ? -hsel : hsel;   // (1 - 2 x_k) h_k
-            }
-            if constexpr (gen) {
-                // only the owning lane changes: the other wave skips this
-                // (the flip's byte word chosen by a wave-uniform branch)
-                if (owner) {
-                    const int fb = k % F;
-                    xb ^= 1u << fb;
-                    const uint32_t mb = 0xFFu << (8 * (fb & 3));
-                    if (fb < 4) xbw[0] ^= mb;
-                    else xbw[NXW - 1] ^= mb;
+            // the flip's state changes in one lane of one wave: the other
+            // waves skip this by a wave-uniform branch
+            if (NW == 1 || kw == wr) {
+                int hk = 0;
+                if (NW > 1) hk = readlane(pick_field<F>(h, bit), kl);
+                if (lane == kl) {
+                    if (NW > 1) dEs[par] = xk ? -hk : hk;   // (1 - 2 x_k) h_k
+                    xb ^= 1u << bit;
+                    if constexpr (gen) {
+                        const uint32_t mb = 0xFFu << (8 * (bit & 3));
+                        if (bit < 4) xbw[0] ^= mb;
+                        else xbw[NXW - 1] ^= mb;
+                    }
                 }
-            } else {
-                xb ^= owner ? (1u << (k % F)) : 0u;
             }
             if (sparse) {
                 // only k's neighbours change.  Each wave takes the entries of
