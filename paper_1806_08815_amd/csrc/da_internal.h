@@ -86,7 +86,8 @@ struct StepT {
 
 // Compile-time feature sets of the step kernel (see run_block).
 constexpr int kModePlain = 0, kModeSingle = 1, kModePerStep = 2, kModeDynamic = 4,
-              kModeSparse = 8, kModeWide = 16, kModeDirect = 32, kModeGen = 64;
+              kModeSparse = 8, kModeWide = 16, kModeDirect = 32, kModeGen = 64,
+              kModeNW4 = 128;
 
 struct JobDesc {
     const void *W;

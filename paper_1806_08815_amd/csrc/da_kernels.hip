@@ -121,6 +121,14 @@ __device__ __forceinline__ int readlane(int v, int lane) {
 }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+// a wave-uniform 64-bit value kept in scalar registers (the 64-bit division
+// of the level arithmetic leaves its results in vector registers)
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 
 // Exclusive prefix sum over the wave of c (0 <= c < 32) and the wave total,
 // from ballots of the bits of c.
@@ -309,7 +317,9 @@ size_t run_lds_bytes(int NW, int RPW, int F, int w_lds_bytes, int stage_brk, int
 // LDS-resident and 24-bit update paths drop out of the step loop.
 // kModeDirect carries the direct-table decisions of narrow-band levels;
 // kModeGen the per-draw threshold estimates of wide bands (for jobs that set
-// gth, on levels whose window was measured narrow).
+// gth, on levels whose window was measured narrow); kModeNW4 states that a
+// replica has at most 4 compute waves (the selection's wave records are all
+// read before the search).
 // BATCH: the persistent batched kernel, whose workgroups may hold more waves
 // than the job's replica slots.
 template <typename WT, int F, bool TRACE, bool HELP, bool STAGE, int MODE, bool BATCH = false>
@@ -327,6 +337,8 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     // wave-level quantities are uniform: keep them in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     constexpr bool wide = (MODE & kModeWide) != 0;
+    constexpr bool nw4 = (MODE & kModeNW4) != 0;
+    static_assert(!nw4 || !BATCH, "the batched kernel mixes wave counts");
     const int NW = wide ? max(J.NW, 2) : J.NW;
     const int w_lds = wide ? 0 : J.w_lds;
     const int NH = HELP ? J.NH : 0;
@@ -615,10 +627,15 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     StepT st_next{0.0, -1, -1};
     if (perstep && !helper && s0 < s1) st_next = J.stepT[s0];
 
-    bool pend = false;   // NW > 1: the previous step's energy change is in dEs
+    // NW > 1: step s adds the energy change of step s - 1 from dEs (zero when
+    // no flip was taken; both slots start at zero)
+    if (NW > 1 && !helper && active && wr == 0 && lane == 0) {
+        dEs[0] = 0;
+        dEs[1] = 0;
+    }
     // countdowns (steps left, steps to the next level) tested for equality
     // only: 64-bit equality is a scalar compare, ordering is not
-    int64_t to_next = s_next - s0;
+    int64_t to_next = uniform64(s_next - s0);
     int64_t s = s0;
     // generator waves: step s + 1's draws during step s, and the same
     // barriers as the compute waves, level changes included
@@ -627,7 +644,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             if (to_next == 0) {
                 lvl = level_of(s, J.L, J.S);
                 s_next = next_level_step(lvl, J.L, J.S);
-                to_next = s_next - s;
+                to_next = uniform64(s_next - s);
                 hd = J.hdr[lvl];
                 if (stage) stage_brackets();
             }
@@ -665,13 +682,15 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     int rec_o = (int)(s0 & 1) * RS;
     int drw_o = (int)((s0 + 1) & 1) * NH * 64;
     int est_o = (int)((s0 + 1) & 1) * 2 * NH * 64;
-    for (int64_t left = (HELP && helper) ? 0 : (s1 > s0 ? s1 - s0 : 0); left != 0;
-         --left, ++s, --to_next, rec_o = RS - rec_o, drw_o = NH * 64 - drw_o,
-                 est_o = 2 * NH * 64 - est_o) {
+    // (the loop ends at step s1e, compared for equality; the random-number
+    // waves have already run their steps, and s stands past them)
+    const int64_t s1e = (HELP && helper) ? s : (s1 > s0 ? s1 : s0);
+    for (; s != s1e; ++s, --to_next, rec_o = RS - rec_o, drw_o = NH * 64 - drw_o,
+                     est_o = 2 * NH * 64 - est_o) {
         if (to_next == 0) {
             lvl = level_of(s, J.L, J.S);
             s_next = next_level_step(lvl, J.L, J.S);
-            to_next = s_next - s;
+            to_next = uniform64(s_next - s);
             hd = J.hdr[lvl];
             gen_level();
             if (stage) {
@@ -687,7 +706,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             Tstep = st_next.T;
             hd.tmin = st_next.tmin;
             hd.tmax = st_next.tmax;
-            if (left != 1) st_next = J.stepT[s + 1];
+            if (s + 1 != s1e) st_next = J.stepT[s + 1];
         }
         int d[F];
         uint32_t acc = 0;
@@ -989,7 +1008,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
             int scan = tw;
             scan += __builtin_amdgcn_update_dpp(0, scan, 0x111, 0xf, 0xf, false);  // row_shr:1
             scan += __builtin_amdgcn_update_dpp(0, scan, 0x112, 0xf, 0xf, false);  // row_shr:2
-            if (NW > 4) {
+            if (!nw4 && NW > 4) {
                 scan += __builtin_amdgcn_update_dpp(0, scan, 0x114, 0xf, 0xf, false);  // row_shr:4
                 scan += __builtin_amdgcn_update_dpp(0, scan, 0x118, 0xf, 0xf, false);  // row_shr:8
             }
@@ -1002,7 +1021,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 const int ws = (int)__builtin_ctzll(wbal);
                 const int jw = j - (readlane(scan, ws) - readlane(tw, ws));
                 uint32_t r2;
-                if (NW <= 4) {
+                if (nw4 || NW <= 4) {
                     const uint32_t r01 = (ws & 1) ? r4[1] : r4[0];
                     const uint32_t r23 = (ws & 1) ? r4[3] : r4[2];
                     r2 = (ws & 2) ? r23 : r01;
@@ -1028,28 +1047,35 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
 
         // 4. fetch row k of W (the step's only bulk traffic), then, while it
         // is in flight, finish the previous step's energy and best state
-        RowV raw;
-        if (m > 0 && !sparse) {
-            // address-space-typed loads: a generic pointer would make this one
-            // flat load that waits on both the vector and the LDS counters
-            typedef __attribute__((address_space(3))) const RowV LdsRowV;
-            typedef __attribute__((address_space(1))) const RowV GlobalRowV;
-            if (w_lds) raw = *(LdsRowV *)(Wl + (size_t)k * ld + col0);
-            else raw = *(GlobalRowV *)(reinterpret_cast<const WT *>(J.W) + (size_t)k * ld + col0);
-        }
-        // the next step's direct-table decisions (its draws arrived with this
-        // step's exchange); a level change re-reads them after staging
-        if (HELP && direct) lookup_q(rbn, qv);
-        if (NW > 1 && pend) {
-            // the previous step's energy change (written by its owner lane)
-            E += (int64_t)__builtin_amdgcn_readfirstlane(dEp);
-            const bool better = E < bE;
-            bE = better ? E : bE;
-            bxb = better ? xb : bxb;
-            if (TRACE && active && g == 0) T.E[rr * T.stride + (s - 1 - s0)] = E;
-            pend = false;
-        }
+        // (one branch on m: the work between the fetch and its use is written
+        // out in both arms)
+        auto finish_prev = [&]() __attribute__((always_inline)) {
+            // the next step's direct-table decisions (its draws arrived with
+            // this step's exchange); a level change re-reads them after staging
+            if (HELP && direct) lookup_q(rbn, qv);
+            if (NW > 1) {
+                // the previous step's energy change (written by its owner lane)
+                E += (int64_t)__builtin_amdgcn_readfirstlane(dEp);
+                const bool better = E < bE;
+                bE = better ? E : bE;
+                bxb = better ? xb : bxb;
+                if (TRACE && active && g == 0 && s != s0) T.E[rr * T.stride + (s - 1 - s0)] = E;
+            }
+        };
         if (m > 0) {
+            RowV raw;
+            if (!sparse) {
+                // address-space-typed loads: a generic pointer would make this
+                // one flat load that waits on both the vector and the LDS
+                // counters
+                typedef __attribute__((address_space(3))) const RowV LdsRowV;
+                typedef __attribute__((address_space(1))) const RowV GlobalRowV;
+                if (w_lds) raw = *(LdsRowV *)(Wl + (size_t)k * ld + col0);
+                else
+                    raw = *(GlobalRowV *)(reinterpret_cast<const WT *>(J.W) + (size_t)k * ld +
+                                          col0);
+            }
+            finish_prev();
             // apply the flip: state, energy, every field
             const int delta = xk ? -1 : 1;
             // the flip's state changes in one lane of one wave: the other
@@ -1116,11 +1142,11 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 const bool better = E < bE;
                 bE = better ? E : bE;
                 bxb = better ? xb : bxb;
-            } else {
-                pend = true;
             }
             eoff = 0;
         } else {
+            finish_prev();
+            if (NW > 1 && wr == 0 && lane == 0) dEs[par] = 0;
             // min(E_off + inc, 2^30) without leaving int32 (E_off, inc in [0, 2^30])
             eoff = min(eoff, eoff_cap) + J.eoff_inc;
             k = -1;
@@ -1143,7 +1169,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     if (NW > 1 || HELP) {
         // the last step's energy change
         __syncthreads();
-        if (pend) {
+        if (NW > 1 && !helper && s1e != s0) {
             E += (int64_t)dEs[(int)((s1 - 1) & 1)];
             if (E < bE) {
                 bE = E;
@@ -1610,8 +1636,14 @@ int launch_run_t(const JobDesc &J, const TraceDesc &T, int blocks, int threads, 
                 if constexpr (F >= 4) {
                     // per-draw estimates, evaluated by the compute lanes
                     if (J.gth && wide) {
-                        hipLaunchKernelGGL((k_run<WT, F, false, HELP, true, kModeWide | kModeGen>),
-                                           g, b, lds, S(stream), J, T);
+                        if (J.NW <= 4)
+                            hipLaunchKernelGGL(
+                                (k_run<WT, F, false, HELP, true, kModeWide | kModeGen | kModeNW4>),
+                                g, b, lds, S(stream), J, T);
+                        else
+                            hipLaunchKernelGGL(
+                                (k_run<WT, F, false, HELP, true, kModeWide | kModeGen>), g, b, lds,
+                                S(stream), J, T);
                         return (int)hipGetLastError();
                     }
                 }
@@ -1666,8 +1698,13 @@ int launch_run_t(const JobDesc &J, const TraceDesc &T, int blocks, int threads, 
         case kModePlain:
             if constexpr (F >= 4) {
                 if (J.gth && wide && !J.q8) {
-                    hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, kModeWide | kModeGen>), g,
-                                       b, lds, S(stream), J, T);
+                    if (J.NW <= 4)
+                        hipLaunchKernelGGL(
+                            (k_run<WT, F, TRACE, HELP, true, kModeWide | kModeGen | kModeNW4>), g,
+                            b, lds, S(stream), J, T);
+                    else
+                        hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, kModeWide | kModeGen>),
+                                           g, b, lds, S(stream), J, T);
                     break;
                 }
             }
