@@ -472,7 +472,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         s_next = INT64_MAX;
     } else {
         lvl = level_of(s0, J.L, J.S);
-        s_next = next_level_step(lvl, J.L, J.S);
+        s_next = uniform64(next_level_step(lvl, J.L, J.S));
     }
     LevelHdr hd = J.hdr[lvl];
     bool direct = false;   // this level decides in-band flips by its direct table
@@ -685,12 +685,12 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     // (the loop ends at step s1e, compared for equality; the random-number
     // waves have already run their steps, and s stands past them)
     const int64_t s1e = (HELP && helper) ? s : (s1 > s0 ? s1 : s0);
-    for (; s != s1e; ++s, --to_next, rec_o = RS - rec_o, drw_o = NH * 64 - drw_o,
+    // (a level opens at step s_next: the compute waves compare the step with it)
+    for (; s != s1e; ++s, rec_o = RS - rec_o, drw_o = NH * 64 - drw_o,
                      est_o = 2 * NH * 64 - est_o) {
-        if (to_next == 0) {
+        if (s == s_next) {
             lvl = level_of(s, J.L, J.S);
-            s_next = next_level_step(lvl, J.L, J.S);
-            to_next = uniform64(s_next - s);
+            s_next = uniform64(next_level_step(lvl, J.L, J.S));
             hd = J.hdr[lvl];
             gen_level();
             if (stage) {
@@ -1017,7 +1017,10 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 const uint32_t v = HELP ? (uint32_t)__builtin_amdgcn_readfirstlane((int)vs)
                                         : philox_x_uniform(0u, (uint32_t)s, rid, kTagSelect, k0, k1);
                 const int j = (int)(((uint64_t)v * (uint32_t)m) >> 32);
-                const uint64_t wbal = ballot(scan > j) & ((1ull << NW) - 1ull);
+                // (lane NW - 1 holds m > j, so the first lane found is a wave
+                // index; with four-lane windows the mask is not needed)
+                const uint64_t wbal =
+                    nw4 ? ballot(scan > j) : ballot(scan > j) & ((1ull << NW) - 1ull);
                 const int ws = (int)__builtin_ctzll(wbal);
                 const int jw = j - (readlane(scan, ws) - readlane(tw, ws));
                 uint32_t r2;
@@ -1088,8 +1091,8 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                     xb ^= 1u << bit;
                     if constexpr (gen) {
                         const uint32_t mb = 0xFFu << (8 * (bit & 3));
-                        if (bit < 4) xbw[0] ^= mb;
-                        else xbw[NXW - 1] ^= mb;
+                        xbw[0] ^= bit < 4 ? mb : 0u;
+                        if (NXW > 1) xbw[NXW - 1] ^= bit < 4 ? 0u : mb;
                     }
                 }
             }
