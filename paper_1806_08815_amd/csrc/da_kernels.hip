@@ -1711,7 +1711,11 @@ int launch_run_t(const JobDesc &J, const TraceDesc &T, int blocks, int threads, 
                     break;
                 }
             }
-            if (J.q8 && wide)
+            if (J.q8 && wide && J.NW <= 4)
+                hipLaunchKernelGGL(
+                    (k_run<WT, F, TRACE, HELP, true, kModeWide | kModeDirect | kModeNW4>), g, b,
+                    lds, S(stream), J, T);
+            else if (J.q8 && wide)
                 hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, kModeWide | kModeDirect>), g,
                                    b, lds, S(stream), J, T);
             else if (J.q8)
