@@ -1650,7 +1650,10 @@ int launch_run_t(const JobDesc &J, const TraceDesc &T, int blocks, int threads, 
                         return (int)hipGetLastError();
                     }
                 }
-                if (wide)
+                if (wide && J.NW <= 4)
+                    hipLaunchKernelGGL((k_run<WT, F, false, HELP, true, kModeWide | kModeNW4>), g,
+                                       b, lds, S(stream), J, T);
+                else if (wide)
                     hipLaunchKernelGGL((k_run<WT, F, false, HELP, true, kModeWide>), g, b, lds,
                                        S(stream), J, T);
                 else
@@ -1659,7 +1662,10 @@ int launch_run_t(const JobDesc &J, const TraceDesc &T, int blocks, int threads, 
                 return (int)hipGetLastError();
             }
         }
-        if (wide)
+        if (wide && J.NW <= 4)
+            hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, false, kModeWide | kModeNW4>), g, b, lds,
+                               S(stream), J, T);
+        else if (wide)
             hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, false, kModeWide>), g, b, lds,
                                S(stream), J, T);
         else
@@ -1721,6 +1727,9 @@ int launch_run_t(const JobDesc &J, const TraceDesc &T, int blocks, int threads, 
             else if (J.q8)
                 hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, kModeDirect>), g, b, lds,
                                    S(stream), J, T);
+            else if (wide && J.NW <= 4)
+                hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, kModeWide | kModeNW4>), g, b,
+                                   lds, S(stream), J, T);
             else if (wide)
                 hipLaunchKernelGGL((k_run<WT, F, TRACE, HELP, true, kModeWide>), g, b, lds,
                                    S(stream), J, T);
