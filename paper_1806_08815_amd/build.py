@@ -50,7 +50,7 @@ def build_library(verbose: bool = False) -> str:
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     common = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-ffp-contract=off",
-              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-falign-loops=64",
               "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
     build_id = source_hash()
 

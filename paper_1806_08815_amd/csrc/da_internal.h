@@ -224,14 +224,13 @@ __host__ __device__ inline SlotLayout slot_layout(int NW, int NH, int dhF = 0, b
         L.vring = off;
         off += 128 * 4;
         off = (off + 15) & ~15;
+        // Philox blocks of two steps, [2][NH * 64] int4; with per-draw
+        // estimates each block is followed by its draws' estimates G(u)
+        // (draws 0..3, then 4..7), [2][NH * 64][3] int4, so one address and
+        // fixed offsets reach all three
         L.draws = off;
-        off += 2 * NH * 64 * 16;
-        if (gen) {
-            // per-draw estimates G(u) of each step, [2][2][NH * 64] int4: part 0
-            // holds a block's draws 0..3, part 1 its draws 4..7
-            L.est = off;
-            off += 2 * 2 * NH * 64 * 16;
-        }
+        L.est = off;
+        off += 2 * NH * 64 * 16 * (gen ? 3 : 1);
     }
     if (dhF > 0) {
         off = (off + 15) & ~15;

@@ -405,8 +405,11 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     uint32_t *rec = reinterpret_cast<uint32_t *>(sel + SL.rec);    // [2][RS]
     int *dEs = reinterpret_cast<int *>(sel + SL.dEs);              // [2]
     uint32_t *vring = reinterpret_cast<uint32_t *>(sel + SL.vring);  // [128] selection draws
-    uint4 *draws = reinterpret_cast<uint4 *>(sel + SL.draws);      // [2][NH*64] Philox blocks
-    int4 *est = reinterpret_cast<int4 *>(sel + SL.est);            // [2][2][NH*64] estimates
+    // Philox blocks by step parity, each followed by its two int4 of estimates
+    // in the estimate variants: block b of parity p at draws[p * PB + b * BS]
+    uint4 *draws = reinterpret_cast<uint4 *>(sel + SL.draws);
+    constexpr int BS = ((MODE & kModeGen) != 0) ? 3 : 1;
+    const int PB = NH * 64 * BS;
     // sparse rows: this wave's field-delta buffer [64 * F], kept all zero between steps
     int *dh = reinterpret_cast<int *>(sel + SL.dh) + (helper ? 0 : wr) * 64 * F;
     if (sparse && !helper) {
@@ -536,7 +539,8 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         const int b = g;   // Philox block of this generator lane
         if (active && b < nblk) {
             const uint4 r = philox((uint32_t)b, (uint32_t)st, rid, kTagMetropolis, k0, k1);
-            draws[(int)(st & 1) * NH * 64 + b] = r;
+            uint4 *slot = draws + (int)(st & 1) * PB + b * BS;
+            slot[0] = r;
             if (gen && ggth) {
                 // draw 2q of the block is the low half of word q, 2q + 1 the high half
                 int4 e0, e1;
@@ -548,9 +552,9 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
                 e1.y = draw_estimate(r.z >> 16, gga, ggb);
                 e1.z = draw_estimate(r.w & 0xFFFFu, gga, ggb);
                 e1.w = draw_estimate(r.w >> 16, gga, ggb);
-                int4 *dst = est + (int)(st & 1) * 2 * NH * 64;
-                dst[b] = e0;
-                dst[NH * 64 + b] = e1;
+                int4 *dst = reinterpret_cast<int4 *>(slot);
+                dst[1] = e0;
+                dst[2] = e1;
             }
         }
         // selection draws 64 steps at a time, one step per lane, at the first
@@ -564,44 +568,58 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         }
     };
     // compute waves: this lane's draws of step st (written by the generators)
-    // (o: element offset of the ring slot, (st & 1) * NH * 64 for step st)
+    // (o: element offset of the ring slot, (st & 1) * PB for step st)
+    // (lanes past the last variable only hold ghost flips: their block index
+    // is clamped, so they read a block in bounds)
+    const int dblk = min(i0 >> 3, NH * 64 - 1);
     auto consume_at = [&](int o, uint4 (&dst)[NB]) {
-        // lanes past the last variable only hold ghost flips: clamp their reads
-        const uint4 *src = draws + o;
-        if (F >= 8) {
-#pragma unroll
-            for (int q = 0; q < NB; ++q) dst[q] = src[min((i0 >> 3) + q, NH * 64 - 1)];
-        } else if (F == 4) {
-            const uint2 *s2 = reinterpret_cast<const uint2 *>(src);
-            const uint2 p = s2[min(i0 >> 2, 2 * NH * 64 - 1)];   // half of block i0 >> 3
-            dst[0] = make_uint4(p.x, p.y, p.x, p.y);
+        static_assert(NB == 1, "one Philox block per lane");
+        if constexpr (BS > 1) {
+            // (estimate variants: the block among its estimates)
+            const uint4 *src = draws + o + dblk * BS;
+            if (F >= 8) {
+                dst[0] = src[0];
+            } else {
+                const uint2 p = reinterpret_cast<const uint2 *>(src)[(i0 >> 2) & 1];   // half
+                dst[0] = make_uint4(p.x, p.y, p.x, p.y);
+            }
         } else {
-            const uint32_t *s1 = reinterpret_cast<const uint32_t *>(src);
-            const uint32_t w = s1[min(i0 >> 1, 4 * NH * 64 - 1)];   // word of block i0 >> 3
-            dst[0] = make_uint4(w, w, w, w);
+            const uint4 *src = draws + o;
+            if (F >= 8) {
+                dst[0] = src[dblk];
+            } else if (F == 4) {
+                const uint2 *s2 = reinterpret_cast<const uint2 *>(src);
+                const uint2 p = s2[min(i0 >> 2, 2 * NH * 64 - 1)];   // half of block i0 >> 3
+                dst[0] = make_uint4(p.x, p.y, p.x, p.y);
+            } else {
+                const uint32_t *s1 = reinterpret_cast<const uint32_t *>(src);
+                const uint32_t w = s1[min(i0 >> 1, 4 * NH * 64 - 1)];   // word of block i0 >> 3
+                dst[0] = make_uint4(w, w, w, w);
+            }
         }
     };
 
-    auto consume = [&](int64_t st, uint4 (&dst)[NB]) { consume_at((int)(st & 1) * NH * 64, dst); };
+    auto consume = [&](int64_t st, uint4 (&dst)[NB]) { consume_at((int)(st & 1) * PB, dst); };
 
     // compute waves: this lane's per-draw estimates of a step (o: element
-    // offset of its ring slot, (st & 1) * 2 * NH * 64 for step st)
+    // offset of its ring slot, (st & 1) * PB for step st), stored after each
+    // block's draws
     auto read_est_at = [&](int o, int (&dst)[F]) {
-        const int4 *src = est + o;
-        if constexpr (!gen) {
-            (void)src;
-        } else if constexpr (F >= 8) {
-            const int q = min(g, NH * 64 - 1);
-            const int4 a = src[q], b = src[NH * 64 + q];
+        if constexpr (gen && F >= 8) {
+            const int4 *src = reinterpret_cast<const int4 *>(draws + o + dblk * BS);
+            const int4 a = src[1], b = src[2];
             dst[0] = a.x; dst[1] = a.y; dst[2] = a.z; dst[3] = a.w;
             dst[4] = b.x; dst[5] = b.y; dst[6] = b.z; dst[7] = b.w;
-        } else {
-            // four flips per lane: half a block, part g & 1 of block g >> 1
-            const int4 a = src[(g & 1) * NH * 64 + min(g >> 1, NH * 64 - 1)];
+        } else if constexpr (gen) {
+            // four flips per lane: half a block, part (i0 >> 2) & 1 of block i0 >> 3
+            const int4 *src = reinterpret_cast<const int4 *>(draws + o + dblk * BS);
+            const int4 a = src[1 + ((i0 >> 2) & 1)];
             dst[0] = a.x; dst[1] = a.y; dst[2] = a.z; dst[3] = a.w;
+        } else {
+            (void)o;
         }
     };
-    auto read_est = [&](int64_t st, int (&dst)[F]) { read_est_at((int)(st & 1) * 2 * NH * 64, dst); };
+    auto read_est = [&](int64_t st, int (&dst)[F]) { read_est_at((int)(st & 1) * PB, dst); };
 
     uint4 rb[NB];
     int tv[F];   // this step's per-draw estimates (kModeGen)
@@ -680,14 +698,12 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
     // LDS slots by step parity, toggled every step: this step's lane records
     // and the next step's draws and estimates (element offsets)
     int rec_o = (int)(s0 & 1) * RS;
-    int drw_o = (int)((s0 + 1) & 1) * NH * 64;
-    int est_o = (int)((s0 + 1) & 1) * 2 * NH * 64;
+    int drw_o = (int)((s0 + 1) & 1) * PB;
     // (the loop ends at step s1e, compared for equality; the random-number
     // waves have already run their steps, and s stands past them)
     const int64_t s1e = (HELP && helper) ? s : (s1 > s0 ? s1 : s0);
     // (a level opens at step s_next: the compute waves compare the step with it)
-    for (; s != s1e; ++s, rec_o = RS - rec_o, drw_o = NH * 64 - drw_o,
-                     est_o = 2 * NH * 64 - est_o) {
+    for (; s != s1e; ++s, rec_o = RS - rec_o, drw_o = PB - drw_o) {
         if (s == s_next) {
             lvl = level_of(s, J.L, J.S);
             s_next = uniform64(next_level_step(lvl, J.L, J.S));
@@ -957,7 +973,7 @@ __device__ __forceinline__ void run_block(const JobDesc &J, int blk, uint8_t *sm
         uint4 rbn[NB];
         if (HELP) consume_at(drw_o, rbn);
         int tvn[F];
-        if (gen && HELP) read_est_at(est_o, tvn);
+        if (gen && HELP) read_est_at(drw_o, tvn);
         const uint32_t vs = HELP ? vring[(int)(s & 127)] : 0u;
         int dEp = 0, tw = 0;
         uint32_t r4[4] = {0u, 0u, 0u, 0u};
