@@ -5,7 +5,8 @@
 hipcc cross-compiles for gfx950 without a GPU.  Packed FP32 instructions are
 disabled for all device code, and floating-point contraction is off (the one
 floating-point decision on the device, the replica-exchange test, is a single
-IEEE multiply and compare).
+IEEE multiply and compare).  Loops start on 64-byte boundaries, so the step
+loops' speed does not shift with the length of the code in front of them.
 """
 from __future__ import annotations
 
