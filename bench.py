@@ -552,9 +552,9 @@ def main() -> int:
                          "(the known-size reference for memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(replicas shard across GPUs with no per-step communication, see DESIGN.md)",
-              file=sys.stderr)
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
+              "(replicas would shard across GPUs with no per-step communication; that path is "
+              "designed, not built)", file=sys.stderr)
         return 2
 
     import numpy as np
